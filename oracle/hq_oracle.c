@@ -1,0 +1,518 @@
+/*
+ * CPU FP64 oracle of the Conditional Probability Update (CPU) iteration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Only the test-suite, the smoke check and
+ * the benchmark's CPU-baseline leg load it; the library never does, and the
+ * two share no code, header, table or helper.
+ *
+ * What it computes (paper, Section 2 and Section 3.1):
+ *   - the loss system of Section 2.1 (buffer C = 0): N units, J demand nodes
+ *     with arrival rates lam[j] (= lambda f_j), one preference list per node,
+ *     service rate nu[u] per unit; state m is the busy set, unit u = bit u;
+ *   - transition rates, eq. (3): arrival-driven rate into m from m\{u}
+ *     (u in m) is the summed rate of the nodes all of whose units ranked
+ *     before u are busy in m (the product in (3) read with upper limit
+ *     eta_j(u) - 1); service-driven rate into m from m+{u} is nu[u];
+ *   - the coefficients are generated per target state exactly as
+ *     Algorithm 3 does: walk each node's list over the busy units of m and
+ *     credit lam[j] to every busy unit met before the first idle one;
+ *   - Algorithm 1: initial p_n = 1/C(N,n), then outer iterations that sweep
+ *     layers n = 1..N-1 in ascending order with the update (12), the inner
+ *     mu(n) loop (12)+(14) and lambda(n) by (13); p(n) by (10) and
+ *     P(m) = p(|m|) p_|m|(m) (Proposition 1);
+ *   - the global balance residual of (1): sum_m |inflow - outflow| over
+ *     sum_m P(m)(lambda_m + mu_m).
+ *
+ * Inner-loop modes for the mu(n) loop of Algorithm 1:
+ *   ORC_INNER_CLOSED  : the limit of the inner loop.  With layers n-1 and n+1
+ *                       held fixed, (12)+(14) make mu an affine map
+ *                       mu -> A mu + B; the loop converges to B / (1 - A).
+ *   ORC_INNER_LITERAL : repeat (12) then (14) until max |change| <= delta
+ *                       (at least one update, starting from the previous
+ *                       iteration's mu(n)).
+ *   ORC_INNER_ONE     : exactly one update per layer (delta = infinity).
+ *
+ * Parity of the iteration path with the paper's own runs is unpinned: the
+ * paper prints no per-iteration values.  The final distribution is pinned
+ * (by the tests) against dense and sparse direct solves, closed forms and
+ * invariants.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC hq_oracle.c -o libhq_oracle.so -lm
+ * Per-state loops run under OpenMP; every sum is taken sequentially in
+ * increasing state index, so results do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_INNER_CLOSED = 0, ORC_INNER_LITERAL = 1, ORC_INNER_ONE = 2 };
+enum { ORC_STOP_RESIDUAL = 0, ORC_STOP_DELTA = 1 };
+
+/* number of OpenMP threads the oracle will use (1 without OpenMP) */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static int popcount32(uint32_t x) { return __builtin_popcount(x); }
+
+static double binom(int n, int k) {
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return floor(r + 0.5);
+}
+
+/* Algorithm 3 for one target state m: a[u] = arrival-driven rate from
+ * m\{u} into m, for every u (0 for idle u).  For each node j, walk its list
+ * from the most preferred unit; every busy unit met before the first idle
+ * unit receives lam[j]. */
+void orc_up_coefficients(int N, int J, const double* lam, const int32_t* pref,
+                         uint32_t m, double* a) {
+    for (int u = 0; u < N; ++u) a[u] = 0.0;
+    for (int j = 0; j < J; ++j) {
+        const int32_t* z = pref + (size_t)j * N;
+        for (int h = 0; h < N; ++h) {
+            int u = z[h];
+            if (!((m >> u) & 1u)) break; /* first idle unit ends the walk */
+            a[u] += lam[j];
+        }
+    }
+}
+
+/* total service rate mu_m = sum of nu over busy units */
+static double state_mu(int N, const double* nu, uint32_t m) {
+    double s = 0.0;
+    for (int u = 0; u < N; ++u)
+        if ((m >> u) & 1u) s += nu[u];
+    return s;
+}
+
+/* Relative L1 global-balance residual of an unnormalised-or-normalised P
+ * (bitmask order), eq. (1): inflow(m) = sum_{u in m} a(m,u) P(m\u)
+ * + sum_{u notin m} nu_u P(m+u), outflow(m) = P(m)(lambda_m + mu_m), with
+ * lambda_m = Lambda except for the all-busy state (0).  Coefficients come
+ * from Algorithm 3 for each state; returns sum|in-out| / sum outflow.
+ * If `terms` is non-NULL it receives (in - out) per state. */
+double orc_residual(int N, int J, const double* lam, const double* nu,
+                    const int32_t* pref, const double* P, double* terms) {
+    const uint32_t S = 1u << N, full = S - 1u;
+    double Lam = 0.0;
+    for (int j = 0; j < J; ++j) Lam += lam[j];
+    double* diff = (double*)malloc(sizeof(double) * S);
+    double* outf = (double*)malloc(sizeof(double) * S);
+#pragma omp parallel
+    {
+        double* a = (double*)malloc(sizeof(double) * (N > 0 ? N : 1));
+#pragma omp for schedule(dynamic, 256)
+        for (long long mm = 0; mm < (long long)S; ++mm) {
+            uint32_t m = (uint32_t)mm;
+            orc_up_coefficients(N, J, lam, pref, m, a);
+            double in = 0.0;
+            for (int u = 0; u < N; ++u) {
+                uint32_t bit = 1u << u;
+                if (m & bit) in += a[u] * P[m ^ bit];
+                else in += nu[u] * P[m | bit];
+            }
+            double lm = (m == full) ? 0.0 : Lam;
+            double out = P[m] * (lm + state_mu(N, nu, m));
+            diff[m] = in - out;
+            outf[m] = out;
+        }
+        free(a);
+    }
+    double num = 0.0, den = 0.0;
+    for (uint32_t m = 0; m < S; ++m) {
+        num += fabs(diff[m]);
+        den += outf[m];
+        if (terms) terms[m] = diff[m];
+    }
+    free(diff);
+    free(outf);
+    return den > 0.0 ? num / den : 0.0;
+}
+
+/* Layer lists: states of each popcount class in increasing index order. */
+typedef struct {
+    uint32_t* states; /* all 2^N states grouped by layer */
+    size_t* start;    /* start[n] .. start[n+1] */
+} layers_t;
+
+static void build_layers(int N, layers_t* L) {
+    const uint32_t S = 1u << N;
+    L->states = (uint32_t*)malloc(sizeof(uint32_t) * S);
+    L->start = (size_t*)calloc((size_t)N + 2, sizeof(size_t));
+    for (uint32_t m = 0; m < S; ++m) L->start[popcount32(m) + 1]++;
+    for (int n = 0; n <= N; ++n) L->start[n + 1] += L->start[n];
+    size_t* fill = (size_t*)malloc(sizeof(size_t) * ((size_t)N + 1));
+    for (int n = 0; n <= N; ++n) fill[n] = L->start[n];
+    for (uint32_t m = 0; m < S; ++m) L->states[fill[popcount32(m)]++] = m;
+    free(fill);
+}
+
+static void free_layers(layers_t* L) {
+    free(L->states);
+    free(L->start);
+}
+
+/*
+ * Full Algorithm 1.
+ *
+ * Inputs: N (1..26), J >= 1, lam[J] >= 0 with sum > 0, nu[N] > 0,
+ * pref[J*N] (row j: units, most preferred first), inner mode and delta
+ * (LITERAL only), stop mode and tol, max_iters, check_every (residual mode
+ * checks every check_every iterations, and always at max_iters), init_p
+ * (NULL = uniform 1/C(N,n), else conditional probabilities in bitmask order).
+ *
+ * Outputs (caller-allocated):
+ *   P[2^N]     stationary distribution, bitmask order, renormalised to sum 1
+ *   pcond[2^N] conditional layer probabilities p_n(m), bitmask order
+ *   layer[3*(N+1)]  lambda(n), mu(n), p(n) for n = 0..N
+ *   stats[8]   iterations, final residual, sum(P)-1 before renormalising,
+ *              max layer normalisation drift max_n |sum p_n - 1| at the end,
+ *              last max |p^k - p^(k-1)|, coefficient seconds, iteration
+ *              seconds, threads
+ *   trace[max_iters] (nullable): residual after each checked iteration (or
+ *              -1 for unchecked ones)
+ *   layer_trace (nullable): [max_iters * (N+1)] sum p_n after each iteration
+ * Returns 0 on convergence, 1 if max_iters was reached, -1 on bad input.
+ */
+int orc_solve(int N, int J, const double* lam, const double* nu, const int32_t* pref,
+              int inner_mode, double delta, int stop_mode, double tol, int max_iters,
+              int check_every, const double* init_p, double* P, double* pcond,
+              double* layer, double* stats, double* trace, double* layer_trace) {
+    if (N < 1 || N > 26 || J < 1 || max_iters < 1) return -1;
+    if (check_every < 1) check_every = 1;
+    const uint32_t S = 1u << N, full = S - 1u;
+    double Lam = 0.0;
+    for (int j = 0; j < J; ++j) Lam += lam[j];
+    struct timespec t0, t1, t2;
+    clock_gettime(CLOCK_MONOTONIC, &t0);
+
+    /* degenerate: no arrivals, the chain sits in the empty state */
+    if (!(Lam > 0.0)) {
+        for (uint32_t m = 0; m < S; ++m) {
+            P[m] = (m == 0) ? 1.0 : 0.0;
+            pcond[m] = 0.0;
+        }
+        for (int n = 0; n <= N; ++n) {
+            layer[3 * n + 0] = 0.0;
+            layer[3 * n + 1] = 0.0;
+            layer[3 * n + 2] = (n == 0) ? 1.0 : 0.0;
+        }
+        pcond[0] = 1.0;
+        memset(stats, 0, sizeof(double) * 8);
+        stats[7] = orc_threads();
+        return 0;
+    }
+
+    layers_t LY;
+    build_layers(N, &LY);
+
+    /* per-state service rate and the Algorithm-3 coefficient table
+     * (step 2 of Algorithm 1 precomputes every coefficient once) */
+    double* mu = (double*)malloc(sizeof(double) * S);
+    double* coef = (double*)malloc(sizeof(double) * (size_t)S * N);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (long long mm = 0; mm < (long long)S; ++mm) {
+        uint32_t m = (uint32_t)mm;
+        mu[m] = state_mu(N, nu, m);
+        orc_up_coefficients(N, J, lam, pref, m, coef + (size_t)m * N);
+    }
+    clock_gettime(CLOCK_MONOTONIC, &t1);
+
+    double* p = pcond;
+    double* U = (double*)malloc(sizeof(double) * S);
+    double* D = (double*)malloc(sizeof(double) * S);
+    double* pnew = (double*)malloc(sizeof(double) * S);
+    double* lamn = (double*)malloc(sizeof(double) * (N + 1));
+    double* mun = (double*)malloc(sizeof(double) * (N + 1));
+
+    /* initialisation (Algorithm 1, step 2) */
+    for (int n = 0; n <= N; ++n) {
+        double c = 1.0 / binom(N, n);
+        for (size_t i = LY.start[n]; i < LY.start[n + 1]; ++i) {
+            uint32_t m = LY.states[i];
+            p[m] = init_p ? init_p[m] : c;
+        }
+    }
+    p[0] = 1.0;    /* p_0(empty) = 1 */
+    p[full] = 1.0; /* p_N(full) = 1 */
+    /* initial layer scalars from (13)-(14) */
+    for (int n = 0; n <= N; ++n) {
+        double sl = 0.0, sm = 0.0;
+        for (size_t i = LY.start[n]; i < LY.start[n + 1]; ++i) {
+            uint32_t m = LY.states[i];
+            sl += p[m] * ((m == full) ? 0.0 : Lam);
+            sm += p[m] * mu[m];
+        }
+        lamn[n] = sl;
+        mun[n] = sm;
+    }
+
+    int k = 0, converged = 0;
+    double res = -1.0, maxdelta = 0.0;
+    while (k < max_iters) {
+        ++k;
+        maxdelta = 0.0;
+        for (int n = 1; n <= N - 1; ++n) {
+            const size_t b = LY.start[n], e = LY.start[n + 1];
+            const double Lprev = lamn[n - 1];            /* lambda^k(n-1), already updated */
+            const double beta = lamn[n] / mun[n + 1];    /* lambda^{k-1}(n) / mu^{k-1}(n+1) */
+            /* the two r-independent parts of (12) for every state of the layer */
+#pragma omp parallel for schedule(dynamic, 256)
+            for (long long ii = (long long)b; ii < (long long)e; ++ii) {
+                uint32_t m = LY.states[ii];
+                const double* a = coef + (size_t)m * N;
+                double up = 0.0, dn = 0.0;
+                for (int u = 0; u < N; ++u) {
+                    uint32_t bit = 1u << u;
+                    if (m & bit) up += a[u] * p[m ^ bit]; /* from layer n-1, lambda_lm */
+                    else dn += nu[u] * p[m | bit];        /* from layer n+1, mu_lm = nu_u */
+                }
+                double den = Lam + mu[m]; /* lambda_m + mu_m, lambda_m = Lambda for n < N */
+                U[m] = up / den;
+                D[m] = dn / den;
+            }
+            double mu_star;
+            if (inner_mode == ORC_INNER_CLOSED) {
+                /* p(m) = (mu/Lprev) U(m) + beta D(m);  mu' = sum mu_m p(m) = A mu + B */
+                double sA = 0.0, sB = 0.0;
+                for (size_t i = b; i < e; ++i) {
+                    uint32_t m = LY.states[i];
+                    sA += mu[m] * U[m];
+                    sB += mu[m] * D[m];
+                }
+                double A = sA / Lprev, B = beta * sB;
+                mu_star = B / (1.0 - A);
+                for (size_t i = b; i < e; ++i) {
+                    uint32_t m = LY.states[i];
+                    pnew[m] = (mu_star / Lprev) * U[m] + beta * D[m];
+                }
+            } else {
+                /* literal inner loop, starting from mu^{k-1}(n) and the previous
+                 * iteration's layer values */
+                double mu_cur = mun[n];
+                for (size_t i = b; i < e; ++i) pnew[LY.states[i]] = p[LY.states[i]];
+                for (int r = 0;; ++r) {
+                    double change = 0.0, smu = 0.0;
+                    for (size_t i = b; i < e; ++i) {
+                        uint32_t m = LY.states[i];
+                        double v = (mu_cur / Lprev) * U[m] + beta * D[m];
+                        double d = fabs(v - pnew[m]);
+                        if (d > change) change = d;
+                        pnew[m] = v;
+                        smu += mu[m] * v;
+                    }
+                    mu_cur = smu;
+                    if (inner_mode == ORC_INNER_ONE) break;
+                    if (change <= delta || r > 1000000) break;
+                }
+                mu_star = mu_cur;
+            }
+            (void)mu_star;
+            /* commit the layer and its scalars (13)-(14) */
+            double sp = 0.0, smu = 0.0;
+            for (size_t i = b; i < e; ++i) {
+                uint32_t m = LY.states[i];
+                double d = fabs(pnew[m] - p[m]);
+                if (d > maxdelta) maxdelta = d;
+                p[m] = pnew[m];
+                sp += p[m];
+                smu += mu[m] * p[m];
+            }
+            lamn[n] = Lam * sp;
+            mun[n] = smu;
+        }
+        if (layer_trace) {
+            for (int n = 0; n <= N; ++n) {
+                double s = 0.0;
+                for (size_t i = LY.start[n]; i < LY.start[n + 1]; ++i) s += p[LY.states[i]];
+                layer_trace[(size_t)(k - 1) * (N + 1) + n] = s;
+            }
+        }
+        int check = (stop_mode == ORC_STOP_RESIDUAL) && ((k % check_every) == 0 || k == max_iters);
+        if (trace) trace[k - 1] = -1.0;
+        if (stop_mode == ORC_STOP_DELTA) {
+            if (maxdelta <= tol) {
+                converged = 1;
+                break;
+            }
+        } else if (check) {
+            /* assemble P (10) and measure the balance residual (1) */
+            double g = 1.0, G = 1.0;
+            for (int n = 1; n <= N; ++n) {
+                g = g * lamn[n - 1] / mun[n];
+                G += g;
+            }
+            g = 1.0;
+            for (int n = 0; n <= N; ++n) {
+                if (n > 0) g = g * lamn[n - 1] / mun[n];
+                double pn = g / G;
+                for (size_t i = LY.start[n]; i < LY.start[n + 1]; ++i) {
+                    uint32_t m = LY.states[i];
+                    P[m] = pn * p[m];
+                }
+            }
+            /* residual with the precomputed coefficients */
+            double num = 0.0, den = 0.0;
+            for (uint32_t m = 0; m < S; ++m) {
+                const double* a = coef + (size_t)m * N;
+                double in = 0.0;
+                for (int u = 0; u < N; ++u) {
+                    uint32_t bit = 1u << u;
+                    if (m & bit) in += a[u] * P[m ^ bit];
+                    else in += nu[u] * P[m | bit];
+                }
+                double out = P[m] * (((m == full) ? 0.0 : Lam) + mu[m]);
+                num += fabs(in - out);
+                den += out;
+            }
+            res = num / den;
+            if (trace) trace[k - 1] = res;
+            if (res <= tol) {
+                converged = 1;
+                break;
+            }
+        }
+    }
+    clock_gettime(CLOCK_MONOTONIC, &t2);
+
+    /* Algorithm 1 steps 16-17: p(n) by (10), P = p(|m|) p_|m|(m) */
+    double g = 1.0, G = 1.0;
+    for (int n = 1; n <= N; ++n) {
+        g = g * lamn[n - 1] / mun[n];
+        G += g;
+    }
+    g = 1.0;
+    double total = 0.0, drift = 0.0;
+    for (int n = 0; n <= N; ++n) {
+        if (n > 0) g = g * lamn[n - 1] / mun[n];
+        double pn = g / G;
+        layer[3 * n + 0] = lamn[n];
+        layer[3 * n + 1] = mun[n];
+        layer[3 * n + 2] = pn;
+        double s = 0.0;
+        for (size_t i = LY.start[n]; i < LY.start[n + 1]; ++i) {
+            uint32_t m = LY.states[i];
+            P[m] = pn * p[m];
+            s += p[m];
+        }
+        if (fabs(s - 1.0) > drift) drift = fabs(s - 1.0);
+    }
+    for (uint32_t m = 0; m < S; ++m) total += P[m];
+    for (uint32_t m = 0; m < S; ++m) P[m] /= total;
+    if (stop_mode == ORC_STOP_DELTA || res < 0.0 || !converged)
+        res = orc_residual(N, J, lam, nu, pref, P, NULL);
+
+    stats[0] = k;
+    stats[1] = res;
+    stats[2] = total - 1.0;
+    stats[3] = drift;
+    stats[4] = maxdelta;
+    stats[5] = (t1.tv_sec - t0.tv_sec) + 1e-9 * (t1.tv_nsec - t0.tv_nsec);
+    stats[6] = (t2.tv_sec - t1.tv_sec) + 1e-9 * (t2.tv_nsec - t1.tv_nsec);
+    stats[7] = orc_threads();
+
+    free(mu);
+    free(coef);
+    free(U);
+    free(D);
+    free(pnew);
+    free(lamn);
+    free(mun);
+    free_layers(&LY);
+    return converged ? 0 : 1;
+}
+
+/*
+ * One layer update of (12) for a sample of states, from caller-supplied
+ * neighbour layers, with Algorithm-3 coefficients generated on demand for
+ * each state (no table).  pl and pu are conditional probabilities in
+ * bitmask order (only entries of layers n-1 and n+1 are read).  For each
+ * states[i] (all in layer n, 1 <= n <= N-1): out[i] = alpha*U + beta*D,
+ * U = sum_{u in m} a(m,u) pl(m\u) / (Lambda+mu_m),
+ * D = sum_{u notin m} nu_u pu(m+u) / (Lambda+mu_m).
+ * If outU/outD are non-NULL they receive U and D.
+ */
+void orc_update_states(int N, int J, const double* lam, const double* nu,
+                       const int32_t* pref, long long count, const uint32_t* states,
+                       const double* pl, const double* pu, double alpha, double beta,
+                       double* out, double* outU, double* outD) {
+    double Lam = 0.0;
+    for (int j = 0; j < J; ++j) Lam += lam[j];
+#pragma omp parallel
+    {
+        double* a = (double*)malloc(sizeof(double) * N);
+#pragma omp for schedule(dynamic, 64)
+        for (long long i = 0; i < count; ++i) {
+            uint32_t m = states[i];
+            orc_up_coefficients(N, J, lam, pref, m, a);
+            double up = 0.0, dn = 0.0;
+            for (int u = 0; u < N; ++u) {
+                uint32_t bit = 1u << u;
+                if (m & bit) up += a[u] * pl[m ^ bit];
+                else dn += nu[u] * pu[m | bit];
+            }
+            double den = Lam + state_mu(N, nu, m);
+            double Uv = up / den, Dv = dn / den;
+            out[i] = alpha * Uv + beta * Dv;
+            if (outU) outU[i] = Uv;
+            if (outD) outD[i] = Dv;
+        }
+        free(a);
+    }
+}
+
+/* Sums over a whole layer n of U(m), mu_m U(m), D(m), mu_m D(m) (U, D as in
+ * orc_update_states), taken in increasing state order.  out[4]. */
+void orc_layer_sums(int N, int J, const double* lam, const double* nu, const int32_t* pref,
+                    int n, const double* pl, const double* pu, double* out) {
+    const uint32_t S = 1u << N;
+    long long cnt = 0;
+    for (uint32_t m = 0; m < S; ++m)
+        if (popcount32(m) == n) ++cnt;
+    uint32_t* st = (uint32_t*)malloc(sizeof(uint32_t) * (cnt > 0 ? cnt : 1));
+    long long c = 0;
+    for (uint32_t m = 0; m < S; ++m)
+        if (popcount32(m) == n) st[c++] = m;
+    double* o = (double*)malloc(sizeof(double) * (cnt > 0 ? cnt : 1));
+    double* U = (double*)malloc(sizeof(double) * (cnt > 0 ? cnt : 1));
+    double* D = (double*)malloc(sizeof(double) * (cnt > 0 ? cnt : 1));
+    orc_update_states(N, J, lam, nu, pref, cnt, st, pl, pu, 0.0, 0.0, o, U, D);
+    double s[4] = {0, 0, 0, 0};
+    for (long long i = 0; i < cnt; ++i) {
+        double mum = state_mu(N, nu, st[i]);
+        s[0] += U[i];
+        s[1] += mum * U[i];
+        s[2] += D[i];
+        s[3] += mum * D[i];
+    }
+    for (int i = 0; i < 4; ++i) out[i] = s[i];
+    free(st);
+    free(o);
+    free(U);
+    free(D);
+}
+
+/* Per-unit busy probabilities rho_u = sum_{m containing u} P(m), and the
+ * number-busy marginal pn[n] = sum_{|m| = n} P(m), from P in bitmask order. */
+void orc_marginals(int N, const double* P, double* rho, double* pn) {
+    const uint32_t S = 1u << N;
+    for (int u = 0; u < N; ++u) rho[u] = 0.0;
+    for (int n = 0; n <= N; ++n) pn[n] = 0.0;
+    for (uint32_t m = 0; m < S; ++m) {
+        pn[popcount32(m)] += P[m];
+        for (int u = 0; u < N; ++u)
+            if ((m >> u) & 1u) rho[u] += P[m];
+    }
+}
