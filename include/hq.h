@@ -1,0 +1,193 @@
+/*
+ * hq.h — C ABI of the MI355X hypercube queueing solver (libhq.so).
+ *
+ * The library computes the stationary distribution P of the 2^N-state
+ * busy/idle loss CTMC of the spatial hypercube model with heterogeneous
+ * service rates (Section 2.1: N units, J demand nodes, each node dispatches
+ * to its first idle preferred unit, calls finding every unit busy are lost),
+ * by the Conditional Probability Update iteration (Algorithm 1) over the
+ * birth-death reformulation (Proposition 1, eqs. (8)-(10)).
+ *
+ * Conventions shared by every entry point:
+ *   - State m is a bitmask: bit u set <=> unit u busy (the index y(B_m) of
+ *     Section 3.2 with unit i = bit i-1).  Exported P is in this order.
+ *   - Rates are in any consistent time unit; P is invariant under scaling
+ *     all rates together.
+ *   - Inputs are copied during the call; the caller may free them on return.
+ *     Output arrays are caller-allocated host memory unless stated.
+ *   - Every failure returns a status code (never aborts or throws across the
+ *     ABI) and sets a thread-local message readable with hq_last_error().
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Errors from the HIP runtime are reported as HQ_ERR_DEVICE.
+ */
+#ifndef HQ_H
+#define HQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HQ_MAX_N 30 /* 2^30 states; colex ranks and layer offsets fit in uint32 */
+
+typedef struct hq_ctx hq_ctx; /* opaque; owns its host and device memory */
+
+typedef enum {
+    HQ_OK = 0,
+    HQ_ERR_INVALID_ARG = 1,  /* bad size, rate, preference row, tolerance, option */
+    HQ_ERR_OUT_OF_MEMORY = 2,/* host or device allocation failed */
+    HQ_ERR_DEVICE = 3,       /* HIP runtime error, or no usable GPU */
+    HQ_ERR_NOT_CONVERGED = 4,/* max_iters reached; the last iterate stays readable */
+    HQ_ERR_NUMERIC = 5,      /* NaN/Inf or a zero denominator in a layer reduction */
+    HQ_ERR_STATE = 6         /* results requested before any solve/iterate */
+} hq_status;
+
+/* storage precision of the conditional-probability vector */
+enum {
+    HQ_FP64 = 0,          /* FP64 state, FP64 arithmetic (default) */
+    HQ_FP32 = 1,          /* FP32 state with per-layer scale, FP64 reductions and residual */
+    HQ_FP32_POLISH64 = 2  /* FP32 sweeps to the FP32 floor, then FP64 sweeps to tol */
+};
+
+/* reading of Algorithm 1's inner mu(n) loop (delta is never stated) */
+enum {
+    HQ_INNER_CLOSED = 0, /* the delta -> 0 limit: mu(n) = B / (1 - A) each layer (two passes) */
+    HQ_INNER_ONE = 1     /* one update per layer (delta = infinity); same fixed point */
+};
+
+/* initial iterate */
+enum {
+    HQ_INIT_UNIFORM = 0, /* p_n(m) = 1 / C(N, n), as Algorithm 1 step 2 */
+    HQ_INIT_PRODUCT = 1, /* p_n(m) proportional to prod_{u in m} x_u, x_u = rho_u / (1 - rho_u), from init_rho */
+    HQ_INIT_STATE = 2,   /* resume: conditional probabilities p_n(m) from init_state (bitmask order) */
+    HQ_INIT_LEARNED = 3  /* product form with rho predicted by the loaded MLP (hq_mlp_load) */
+};
+
+/* stopping rule */
+enum {
+    HQ_STOP_RESIDUAL = 0, /* relative L1 balance residual of (1) <= tol (default) */
+    HQ_STOP_DELTA = 1     /* the paper's max_{n,m} |p^k - p^(k-1)| <= tol (Algorithm 1 step 3) */
+};
+
+typedef struct {
+    int precision;            /* HQ_FP64 | HQ_FP32 | HQ_FP32_POLISH64 */
+    int inner;                /* HQ_INNER_CLOSED | HQ_INNER_ONE */
+    int init;                 /* HQ_INIT_* */
+    int stop;                 /* HQ_STOP_* */
+    int max_iters;            /* <= 0: default 100000 */
+    int check_every;          /* residual cadence; <= 0: adaptive (predicts the crossing) */
+    int tile_bits;            /* low bits per tile b (4..12); <= 0: choose */
+    int device;               /* HIP device ordinal; < 0: current device */
+    const double* init_rho;   /* [N] per-unit utilisations for HQ_INIT_PRODUCT (copied) */
+    const double* init_state; /* [2^N] conditional probabilities for HQ_INIT_STATE (copied) */
+    void* stream;             /* hipStream_t to run on (e.g. torch's current stream); NULL = own stream */
+} hq_options;
+
+typedef struct {
+    int status;                  /* hq_status of the solve */
+    int iterations;              /* outer iterations (full layer sweeps) performed */
+    int checks;                  /* residual evaluations performed */
+    int fp64_iterations;         /* of which in FP64 (HQ_FP32_POLISH64) */
+    double residual;             /* last relative L1 balance residual (FP64) */
+    double seconds;              /* wall time of the solve (init + sweeps + checks) */
+    double sweep_seconds;        /* device time of the sweeps alone (HIP events) */
+    double state_updates_per_s;  /* (2^N - 2) * iterations / sweep_seconds */
+    double mass_error;           /* sum(P) - 1 before the final renormalisation */
+    double max_layer_drift;      /* max_n |sum_{C_n} p_n - 1| at the end */
+} hq_info;
+
+/* Fill *opts with the defaults (FP64, closed inner form, uniform init,
+ * residual stop, adaptive checks). */
+void hq_default_options(hq_options* opts);
+
+/*
+ * Create a solver for one instance (Section 2.1; Algorithm 1 inputs).
+ *   N          number of units, 1..HQ_MAX_N
+ *   J          number of demand nodes, >= 1
+ *   lambda_j   [J] arrival rate of node j (lambda f_j), finite, >= 0, sum may be 0
+ *   mu_i       [N] service rate of unit i (the paper's nu_i), finite, > 0
+ *   pref_lists [J*N] row j = units 0..N-1 in node j's order of preference,
+ *              most preferred first; each row must be a permutation
+ *   opts       nullable; NULL = defaults
+ *   out        receives the context (NULL on failure)
+ * Preprocessing (unit relabelling, preference trie, per-tile dispatch
+ * tables) and device allocation happen here.  Errors: HQ_ERR_INVALID_ARG,
+ * HQ_ERR_OUT_OF_MEMORY, HQ_ERR_DEVICE.
+ */
+hq_status hq_create(int N, int J, const double* lambda_j, const double* mu_i,
+                    const int32_t* pref_lists, const hq_options* opts, hq_ctx** out);
+
+/*
+ * Run Algorithm 1 from the configured initial iterate until the stopping
+ * rule holds (tol > 0) or max_iters.  info (nullable) receives the
+ * statistics.  Returns HQ_OK, HQ_ERR_NOT_CONVERGED (iterate still readable),
+ * HQ_ERR_NUMERIC, HQ_ERR_DEVICE or HQ_ERR_INVALID_ARG (tol <= 0 or NaN).
+ * With Lambda = 0 the result is P(empty) = 1 and HQ_OK.
+ */
+hq_status hq_solve(hq_ctx* ctx, double tol, hq_info* info);
+
+/*
+ * Marginals of the last iterate (Proposition 1: P(m) = p(|m|) p_|m|(m)):
+ *   rho_u [N]   (nullable) busy probability of each unit, sum_{m containing u} P(m)
+ *   p_n   [N+1] (nullable) number-busy distribution p(n) of (10)
+ * P is renormalised to sum 1 first.  HQ_ERR_STATE before any solve.
+ */
+hq_status hq_marginals(const hq_ctx* ctx, double* rho_u, double* p_n);
+
+/* Export P [2^N] (bitmask order, renormalised to sum 1) to host memory.
+ * HQ_ERR_STATE before any solve. */
+hq_status hq_state(const hq_ctx* ctx, double* P);
+
+/*
+ * Solve several instances (an uneven batch of candidate deployments) to tol
+ * in one persistent launch (Section 3 iteration per instance, independent
+ * instances).  Every context must be on the same device and must have been
+ * created with HQ_FP64 or HQ_FP32 storage.  infos (nullable) [count].
+ * Returns HQ_OK only if every instance converged; per-instance statuses are
+ * in infos.
+ */
+hq_status hq_solve_batch(hq_ctx* const* ctxs, int count, double tol, hq_info* infos);
+
+/* Release a context (NULL-safe). */
+void hq_destroy(hq_ctx* ctx);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* hq_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Inspection entry points (used for parity checks and resumption).
+ * ------------------------------------------------------------------- */
+
+/* Run exactly `iters` outer iterations from the current iterate (the
+ * initial one if none has run), with no residual check.  Lets a caller stop
+ * the GPU at the same iteration count as a reference. */
+hq_status hq_iterate(hq_ctx* ctx, int iters);
+
+/* Reset the iterate to the configured initial one. */
+hq_status hq_reset(hq_ctx* ctx);
+
+/* Relative L1 balance residual of the current iterate, in FP64. */
+hq_status hq_residual(hq_ctx* ctx, double* residual);
+
+/* Conditional layer probabilities p_n(m) [2^N] in bitmask order
+ * (unnormalised values as iterated; the resume format of HQ_INIT_STATE). */
+hq_status hq_conditional(const hq_ctx* ctx, double* pcond);
+
+/* Layer scalars [4*(N+1)]: for n = 0..N, lambda(n), mu(n), p(n), and
+ * alpha_n = mu(n)/lambda(n-1) as last used in the update (12). */
+hq_status hq_layer_scalars(const hq_ctx* ctx, double* out);
+
+/* Export P [2^N] (bitmask order, sum 1) into device memory `dev_P` of the
+ * context's device, on `stream` (NULL = the context's stream). */
+hq_status hq_state_device(const hq_ctx* ctx, double* dev_P, void* stream);
+
+/* Number of units, and the count of states 2^N, of a context. */
+int hq_num_units(const hq_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HQ_H */

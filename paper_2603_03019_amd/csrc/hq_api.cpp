@@ -1,0 +1,907 @@
+// Host side of libhq: the C ABI of include/hq.h, instance preprocessing and
+// the orchestration of Algorithm 1 on one GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hq.h"
+#include "hq_internal.h"
+
+namespace hqk {
+hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
+                        int inner_one, hipStream_t s);
+hipError_t launch_init(bool fp32, const SweepParams& P, const LayerArgs& A, void* x, const double* xu,
+                       const double* given, const uint32_t* orig_bit, hipStream_t s);
+hipError_t launch_scalars(const SweepParams& P, int want_residual, hipStream_t s);
+hipError_t launch_export(bool fp32, const SweepParams& P, const LayerArgs& A, const void* x, double* out,
+                         const uint32_t* orig_bit, int conditional, hipStream_t s);
+hipError_t launch_marginal(bool fp32, const SweepParams& P, const LayerArgs& A, const void* x, double* part,
+                           double* rho, hipStream_t s);
+hipError_t launch_widen(const float* src, double* dst, uint32_t begin, uint32_t count, double factor,
+                        hipStream_t s);
+}  // namespace hqk
+
+namespace {
+
+enum { M_PASS1 = 0, M_WRITE = 1, M_RESID = 2 };
+
+thread_local std::string g_err;
+
+hq_status fail(hq_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HQ_HIP(call)                                   \
+    do {                                               \
+        hipError_t _e = (call);                        \
+        if (_e != hipSuccess) throw HipError{_e, #call}; \
+    } while (0)
+
+template <typename T>
+T* dalloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) throw std::bad_alloc();
+    return static_cast<T*>(p);
+}
+
+template <typename T>
+void h2d(T* d, const std::vector<T>& h, hipStream_t s) {
+    if (!h.empty()) HQ_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+double binom_d(int n, int k) {
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return std::floor(r + 0.5);
+}
+
+}  // namespace
+
+struct hq_ctx {
+    int N = 0, J = 0, b = 0, H = 0, device = 0;
+    double Lam = 0.0;
+    bool lam_zero = false;
+    hq_options opts{};
+    std::vector<double> rho_init;    // relabelled
+    std::vector<double> state_init;  // original bitmask order
+    std::vector<int> orig;           // new label -> original unit
+    std::vector<double> nu;          // relabelled service rates
+    std::vector<TrieNode> nodes;
+    size_t max_groups = 0;
+    std::vector<LayerArgs> layers;   // per layer n = 0..N
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // device memory
+    double* x64 = nullptr;
+    float* x32 = nullptr;
+    double *d_nu = nullptr, *d_mu_lo = nullptr, *d_tcoef = nullptr, *d_scal = nullptr, *d_part = nullptr;
+    double *d_scale64 = nullptr, *d_scale32 = nullptr, *d_rho = nullptr, *d_xu = nullptr, *d_given = nullptr;
+    uint32_t *d_binom = nullptr, *d_layer_off = nullptr, *d_lo_qstart = nullptr, *d_root_off = nullptr,
+             *d_root_list = nullptr, *d_orig_bit = nullptr;
+    uint16_t *d_lo_unrank = nullptr, *d_lo_rank = nullptr;
+    TrieNode* d_nodes = nullptr;
+    unsigned int* d_counters = nullptr;
+    SweepParams P64{}, P32{};
+    bool have_iterate = false;
+    bool active_fp32 = false;  // storage of the current iterate
+    int iterations_done = 0;
+
+    ~hq_ctx() { release(); }
+    void release() {
+        void* ptrs[] = {x64,      x32,        d_nu,        d_mu_lo,    d_tcoef,   d_scal,      d_part,
+                        d_scale64, d_scale32, d_rho,       d_xu,       d_given,   d_binom,     d_layer_off,
+                        d_lo_qstart, d_root_off, d_root_list, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
+                        d_counters};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+        x64 = nullptr;
+        x32 = nullptr;
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        ev0 = ev1 = nullptr;
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+    uint64_t states() const { return 1ull << N; }
+    const SweepParams& params(bool fp32) const { return fp32 ? P32 : P64; }
+    void* xbuf(bool fp32) const { return fp32 ? (void*)x32 : (void*)x64; }
+};
+
+namespace {
+
+// ----------------------------------------------------------------------------
+// preprocessing
+// ----------------------------------------------------------------------------
+
+hq_status validate(int N, int J, const double* lam, const double* mu, const int32_t* pref) {
+    if (N < 1 || N > HQ_MAX_N) return fail(HQ_ERR_INVALID_ARG, "N must be in [1, " + std::to_string(HQ_MAX_N) + "]");
+    if (J < 1) return fail(HQ_ERR_INVALID_ARG, "J must be >= 1");
+    if (!lam || !mu || !pref) return fail(HQ_ERR_INVALID_ARG, "null input array");
+    for (int j = 0; j < J; ++j)
+        if (!std::isfinite(lam[j]) || lam[j] < 0.0)
+            return fail(HQ_ERR_INVALID_ARG, "lambda_j must be finite and >= 0 (node " + std::to_string(j) + ")");
+    for (int u = 0; u < N; ++u)
+        if (!std::isfinite(mu[u]) || !(mu[u] > 0.0))
+            return fail(HQ_ERR_INVALID_ARG, "mu_i must be finite and > 0 (unit " + std::to_string(u) + ")");
+    std::vector<char> seen(N);
+    for (int j = 0; j < J; ++j) {
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int h = 0; h < N; ++h) {
+            int32_t u = pref[(size_t)j * N + h];
+            if (u < 0 || u >= N || seen[u])
+                return fail(HQ_ERR_INVALID_ARG,
+                            "preference row " + std::to_string(j) + " is not a permutation of 0..N-1");
+            seen[u] = 1;
+        }
+    }
+    return HQ_OK;
+}
+
+// Relabel units so that the low label bits (per-lane inside a tile) go to the
+// units demand nodes reach last: weight of unit u = sum_j lambda_j r^h over
+// the rank h of u in node j's list, r = offered load clipped to [0.3, 0.95].
+std::vector<int> relabel(int N, int J, const double* lam, const double* mu, const int32_t* pref) {
+    double L = 0.0, M = 0.0;
+    for (int j = 0; j < J; ++j) L += lam[j];
+    for (int u = 0; u < N; ++u) M += mu[u];
+    const double r = std::min(0.95, std::max(0.3, L / M));
+    std::vector<double> w(N, 0.0);
+    for (int j = 0; j < J; ++j) {
+        double f = lam[j];
+        for (int h = 0; h < N; ++h) {
+            w[pref[(size_t)j * N + h]] += f;
+            f *= r;
+        }
+    }
+    std::vector<int> order(N);
+    for (int u = 0; u < N; ++u) order[u] = u;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] < w[b]; });
+    return order;  // order[new label] = original unit
+}
+
+// Merged preference trie in preorder (node = shared prefix, rate = summed
+// arrival rate of the nodes through it), over relabelled units.
+std::vector<TrieNode> build_trie(int N, int J, const double* lam, const std::vector<int32_t>& rp) {
+    std::vector<int> ids;
+    for (int j = 0; j < J; ++j)
+        if (lam[j] > 0.0) ids.push_back(j);
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+        return std::lexicographical_compare(rp.begin() + (size_t)a * N, rp.begin() + (size_t)(a + 1) * N,
+                                            rp.begin() + (size_t)b * N, rp.begin() + (size_t)(b + 1) * N);
+    });
+    std::vector<TrieNode> nodes;
+    std::vector<uint32_t> path(N, 0);
+    std::vector<uint32_t> skip;
+    int prev = -1;
+    for (int a : ids) {
+        const int32_t* row = rp.data() + (size_t)a * N;
+        int cp = 0;
+        if (prev >= 0) {
+            const int32_t* pr = rp.data() + (size_t)prev * N;
+            while (cp < N && pr[cp] == row[cp]) ++cp;
+            for (int d = cp; d < N; ++d) skip[path[d]] = (uint32_t)nodes.size();
+        }
+        for (int d = cp; d < N; ++d) {
+            TrieNode nd;
+            nd.need = (d > 0 ? nodes[path[d - 1]].need : 0u) | (1u << row[d]);
+            nd.skip_unit = (uint32_t)row[d];
+            nd.rate = 0.0;
+            path[d] = (uint32_t)nodes.size();
+            nodes.push_back(nd);
+            skip.push_back(0);
+        }
+        for (int d = 0; d < N; ++d) nodes[path[d]].rate += lam[a];
+        prev = a;
+    }
+    if (prev >= 0)
+        for (int d = 0; d < N; ++d) skip[path[d]] = (uint32_t)nodes.size();
+    for (size_t i = 0; i < nodes.size(); ++i) nodes[i].skip_unit |= skip[i] << 5;
+    return nodes;
+}
+
+// Per-tile part of the dispatch walk.  For tile T (high units busy iff
+// their bit is set), walk the trie through busy high units: their rates are
+// uniform over the tile's states (tcoef[T][u]).  A low unit ends the uniform
+// walk: its rate is credited per lane iff the unit is busy (tcoef[T][l]),
+// and the subtrees below it become per-lane roots.
+void build_tiles(int N, int b, const std::vector<TrieNode>& nodes, std::vector<double>& tcoef,
+                 std::vector<uint32_t>& root_off, std::vector<uint32_t>& roots) {
+    const int H = N - b;
+    const uint32_t tiles = 1u << H;
+    tcoef.assign((size_t)tiles * N, 0.0);
+    root_off.assign((size_t)tiles + 1, 0);
+    roots.clear();
+    const uint32_t nn = (uint32_t)nodes.size();
+    for (uint32_t T = 0; T < tiles; ++T) {
+        double* tc = tcoef.data() + (size_t)T * N;
+        root_off[T] = (uint32_t)roots.size();
+        const uint32_t Tabs = T << b;
+        uint32_t i = 0;
+        while (i < nn) {
+            const TrieNode& nd = nodes[i];
+            const int u = (int)(nd.skip_unit & 31u);
+            const uint32_t sk = nd.skip_unit >> 5;
+            if (u >= b) {
+                if ((Tabs >> u) & 1u) {
+                    tc[u] += nd.rate;
+                    ++i;
+                } else {
+                    i = sk;
+                }
+            } else {
+                tc[u] += nd.rate;
+                for (uint32_t c = i + 1; c < sk; c = nodes[c].skip_unit >> 5) roots.push_back(c);
+                i = sk;
+            }
+        }
+    }
+    root_off[tiles] = (uint32_t)roots.size();
+}
+
+void setup_params(hq_ctx* c) {
+    SweepParams P{};
+    P.N = c->N;
+    P.b = c->b;
+    P.H = c->H;
+    P.Lam = c->Lam;
+    P.nu = c->d_nu;
+    P.binom = c->d_binom;
+    P.layer_off = c->d_layer_off;
+    P.lo_unrank = c->d_lo_unrank;
+    P.lo_rank = c->d_lo_rank;
+    P.lo_qstart = c->d_lo_qstart;
+    P.mu_lo = c->d_mu_lo;
+    P.tcoef = c->d_tcoef;
+    P.root_off = c->d_root_off;
+    P.root_list = c->d_root_list;
+    P.nodes = c->d_nodes;
+    const int L = c->N + 1;
+    P.sc.lam = c->d_scal + 0 * L;
+    P.sc.mu = c->d_scal + 1 * L;
+    P.sc.alpha = c->d_scal + 2 * L;
+    P.sc.pn = c->d_scal + 3 * L;
+    P.sc.rnum = c->d_scal + 4 * L;
+    P.sc.rden = c->d_scal + 5 * L;
+    P.sc.delta = c->d_scal + 6 * L;
+    P.sc.misc = c->d_scal + 7 * L;
+    P.partials = c->d_part;
+    P.counters = c->d_counters;
+    c->P64 = P;
+    c->P32 = P;
+    c->P64.scale = c->d_scale64;
+    c->P64.inv_scale = c->d_scale64 + L;
+    c->P32.scale = c->d_scale32;
+    c->P32.inv_scale = c->d_scale32 + L;
+}
+
+hq_status create_impl(int N, int J, const double* lam, const double* mu, const int32_t* pref,
+                      const hq_options* opts, hq_ctx** out) {
+    hq_status st = validate(N, J, lam, mu, pref);
+    if (st != HQ_OK) return st;
+    hq_options o;
+    hq_default_options(&o);
+    if (opts) o = *opts;
+    if (o.precision < HQ_FP64 || o.precision > HQ_FP32_POLISH64)
+        return fail(HQ_ERR_INVALID_ARG, "unknown precision");
+    if (o.inner != HQ_INNER_CLOSED && o.inner != HQ_INNER_ONE) return fail(HQ_ERR_INVALID_ARG, "unknown inner mode");
+    if (o.init < HQ_INIT_UNIFORM || o.init > HQ_INIT_LEARNED) return fail(HQ_ERR_INVALID_ARG, "unknown init mode");
+    if (o.init == HQ_INIT_LEARNED) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_LEARNED needs the MLP entry points");
+    if (o.stop != HQ_STOP_RESIDUAL && o.stop != HQ_STOP_DELTA) return fail(HQ_ERR_INVALID_ARG, "unknown stop rule");
+    if (o.init == HQ_INIT_PRODUCT && !o.init_rho) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_PRODUCT needs init_rho");
+    if (o.init == HQ_INIT_STATE && !o.init_state) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_STATE needs init_state");
+    if (o.tile_bits > 0 && (o.tile_bits < 1 || o.tile_bits > HQ_MAXB))
+        return fail(HQ_ERR_INVALID_ARG, "tile_bits must be in [1, 12]");
+    if (o.init == HQ_INIT_PRODUCT)
+        for (int u = 0; u < N; ++u)
+            if (!std::isfinite(o.init_rho[u]) || o.init_rho[u] < 0.0 || o.init_rho[u] > 1.0)
+                return fail(HQ_ERR_INVALID_ARG, "init_rho values must be in [0, 1]");
+
+    std::unique_ptr<hq_ctx> c(new (std::nothrow) hq_ctx());
+    if (!c) return fail(HQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+    c->N = N;
+    c->J = J;
+    c->opts = o;
+    double Lam = 0.0;
+    for (int j = 0; j < J; ++j) Lam += lam[j];
+    c->Lam = Lam;
+    c->lam_zero = !(Lam > 0.0);
+    int b = o.tile_bits > 0 ? o.tile_bits : (N >= 28 ? 12 : 10);
+    if (b > N) b = N;
+    c->b = b;
+    c->H = N - b;
+    if (c->H > HQ_MAXH) return fail(HQ_ERR_INVALID_ARG, "tile_bits too small for this N");
+
+    // relabel units (new label u <-> original unit orig[u])
+    c->orig = relabel(N, J, lam, mu, pref);
+    std::vector<int> newlab(N);
+    for (int u = 0; u < N; ++u) newlab[c->orig[u]] = u;
+    c->nu.resize(N);
+    for (int u = 0; u < N; ++u) c->nu[u] = mu[c->orig[u]];
+    std::vector<int32_t> rp((size_t)J * N);
+    for (size_t i = 0; i < rp.size(); ++i) rp[i] = newlab[pref[i]];
+    if (o.init == HQ_INIT_PRODUCT) {
+        c->rho_init.resize(N);
+        for (int u = 0; u < N; ++u) c->rho_init[u] = o.init_rho[c->orig[u]];
+    }
+    if (o.init == HQ_INIT_STATE) c->state_init.assign(o.init_state, o.init_state + (1ull << N));
+    c->opts.init_rho = nullptr;
+    c->opts.init_state = nullptr;
+
+    c->nodes = build_trie(N, J, lam, rp);
+    std::vector<double> tcoef;
+    std::vector<uint32_t> root_off, roots;
+    build_tiles(N, b, c->nodes, tcoef, root_off, roots);
+
+    // layout tables
+    std::vector<uint32_t> tb(32 * 32, 0);
+    for (int n = 0; n < 32; ++n)
+        for (int k = 0; k <= n; ++k) tb[n * 32 + k] = (uint32_t)binom_d(n, k);
+    std::vector<uint32_t> layer_off(N + 2, 0);
+    for (int n = 0; n <= N; ++n) layer_off[n + 1] = layer_off[n] + (uint32_t)binom_d(N, n);
+    const uint32_t lo = 1u << b;
+    std::vector<uint16_t> lo_unrank, lo_rank(lo);
+    std::vector<uint32_t> lo_qstart(b + 2, 0);
+    for (int q = 0; q <= b; ++q) {
+        lo_qstart[q] = (uint32_t)lo_unrank.size();
+        uint32_t r = 0;
+        for (uint32_t L = 0; L < lo; ++L)
+            if (__builtin_popcount(L) == q) {
+                lo_unrank.push_back((uint16_t)L);
+                lo_rank[L] = (uint16_t)r++;
+            }
+    }
+    lo_qstart[b + 1] = lo;
+    std::vector<double> mu_lo(lo, 0.0);
+    for (uint32_t L = 0; L < lo; ++L)
+        for (int u = 0; u < b; ++u)
+            if ((L >> u) & 1u) mu_lo[L] += c->nu[u];
+    // per-layer segment tables
+    c->layers.resize(N + 1);
+    size_t max_groups = 1;
+    for (int n = 0; n <= N; ++n) {
+        LayerArgs A{};
+        A.n = n;
+        A.qlo = std::max(0, n - c->H);
+        A.qhi = std::min(b, n);
+        uint32_t acc = 0;
+        for (int q = A.qlo; q <= A.qhi; ++q) {
+            A.seg_start[q - A.qlo] = acc;
+            acc += (uint32_t)binom_d(c->H, n - q);
+        }
+        A.seg_start[A.qhi - A.qlo + 1] = acc;
+        A.groups = acc;
+        max_groups = std::max(max_groups, (size_t)acc);
+        c->layers[n] = A;
+    }
+    c->max_groups = max_groups;
+    // storage scales: 1 for FP64; for FP32 the power of two nearest C(N, n)
+    std::vector<double> s64(2 * (N + 1), 1.0), s32(2 * (N + 1));
+    for (int n = 0; n <= N; ++n) {
+        int e = (int)std::lround(std::log2(binom_d(N, n)));
+        s32[n] = std::ldexp(1.0, e);
+        s32[N + 1 + n] = std::ldexp(1.0, -e);
+    }
+    std::vector<uint32_t> orig_bit(N);
+    for (int u = 0; u < N; ++u) orig_bit[u] = 1u << c->orig[u];
+
+    try {
+        if (o.device >= 0) HQ_HIP(hipSetDevice(o.device));
+        HQ_HIP(hipGetDevice(&c->device));
+        if (o.stream) {
+            c->stream = (hipStream_t)o.stream;
+        } else {
+            HQ_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        HQ_HIP(hipEventCreate(&c->ev0));
+        HQ_HIP(hipEventCreate(&c->ev1));
+        const uint64_t S = c->states();
+        if (o.precision != HQ_FP32) c->x64 = dalloc<double>(S);
+        if (o.precision != HQ_FP64) c->x32 = dalloc<float>(S);
+        c->d_nu = dalloc<double>(N);
+        c->d_mu_lo = dalloc<double>(lo);
+        c->d_tcoef = dalloc<double>(tcoef.size());
+        c->d_scal = dalloc<double>(8 * (N + 1) + 8);
+        c->d_part = dalloc<double>(max_groups * 32);
+        c->d_scale64 = dalloc<double>(s64.size());
+        c->d_scale32 = dalloc<double>(s32.size());
+        c->d_rho = dalloc<double>(32);
+        c->d_xu = dalloc<double>(N);
+        c->d_binom = dalloc<uint32_t>(tb.size());
+        c->d_layer_off = dalloc<uint32_t>(layer_off.size());
+        c->d_lo_qstart = dalloc<uint32_t>(lo_qstart.size());
+        c->d_root_off = dalloc<uint32_t>(root_off.size());
+        c->d_root_list = dalloc<uint32_t>(roots.size());
+        c->d_orig_bit = dalloc<uint32_t>(N);
+        c->d_lo_unrank = dalloc<uint16_t>(lo_unrank.size());
+        c->d_lo_rank = dalloc<uint16_t>(lo_rank.size());
+        c->d_nodes = dalloc<TrieNode>(c->nodes.size());
+        c->d_counters = dalloc<unsigned int>(N + 1);
+        hipStream_t s = c->stream;
+        h2d(c->d_nu, c->nu, s);
+        h2d(c->d_mu_lo, mu_lo, s);
+        h2d(c->d_tcoef, tcoef, s);
+        h2d(c->d_scale64, s64, s);
+        h2d(c->d_scale32, s32, s);
+        h2d(c->d_binom, tb, s);
+        h2d(c->d_layer_off, layer_off, s);
+        h2d(c->d_lo_qstart, lo_qstart, s);
+        h2d(c->d_root_off, root_off, s);
+        h2d(c->d_root_list, roots, s);
+        h2d(c->d_orig_bit, orig_bit, s);
+        h2d(c->d_lo_unrank, lo_unrank, s);
+        h2d(c->d_lo_rank, lo_rank, s);
+        h2d(c->d_nodes, c->nodes, s);
+        HQ_HIP(hipMemsetAsync(c->d_counters, 0, sizeof(unsigned int) * (N + 1), s));
+        HQ_HIP(hipMemsetAsync(c->d_scal, 0, sizeof(double) * (8 * (N + 1) + 8), s));
+        if (!c->state_init.empty()) {
+            c->d_given = dalloc<double>(S);
+            HQ_HIP(hipMemcpyAsync(c->d_given, c->state_init.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        HQ_HIP(hipStreamSynchronize(s));
+    } catch (const std::bad_alloc&) {
+        return fail(HQ_ERR_OUT_OF_MEMORY, "device allocation failed");
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    setup_params(c.get());
+    *out = c.release();
+    return HQ_OK;
+}
+
+// ----------------------------------------------------------------------------
+// iteration
+// ----------------------------------------------------------------------------
+
+void run_init(hq_ctx* c, bool fp32) {
+    const int N = c->N;
+    std::vector<double> e(N + 1, 0.0);
+    if (c->opts.init == HQ_INIT_PRODUCT) {
+        std::vector<double> xu(N);
+        for (int u = 0; u < N; ++u) {
+            double r = std::min(std::max(c->rho_init[u], 1e-6), 1.0 - 1e-6);
+            xu[u] = r / (1.0 - r);
+        }
+        // elementary symmetric polynomials e_n(x) in FP64
+        e[0] = 1.0;
+        for (int u = 0; u < N; ++u)
+            for (int n = u + 1; n >= 1; --n) e[n] += xu[u] * e[n - 1];
+        HQ_HIP(hipMemcpyAsync(c->d_xu, xu.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    }
+    const int mode = c->opts.init == HQ_INIT_PRODUCT ? 1 : (c->opts.init == HQ_INIT_STATE ? 2 : 0);
+    for (int n = 0; n <= N; ++n) {
+        LayerArgs A = c->layers[n];
+        A.init_mode = mode;
+        A.e_n = e[n];
+        HQ_HIP(hqk::launch_init(fp32, c->params(fp32), A, c->xbuf(fp32), c->d_xu, c->d_given, c->d_orig_bit,
+                                c->stream));
+    }
+    c->active_fp32 = fp32;
+    c->have_iterate = true;
+    c->iterations_done = 0;
+}
+
+void run_sweep(hq_ctx* c, bool track_delta) {
+    const bool fp32 = c->active_fp32;
+    const int one = c->opts.inner == HQ_INNER_ONE ? 1 : 0;
+    for (int n = 1; n <= c->N - 1; ++n) {
+        const LayerArgs& A = c->layers[n];
+        if (!one) HQ_HIP(hqk::launch_layer(M_PASS1, false, fp32, c->params(fp32), A, c->xbuf(fp32), one, c->stream));
+        HQ_HIP(hqk::launch_layer(M_WRITE, track_delta, fp32, c->params(fp32), A, c->xbuf(fp32), one, c->stream));
+    }
+    c->iterations_done++;
+}
+
+// residual of the current iterate; also refreshes p(n) and the mass.
+void run_residual(hq_ctx* c, double misc[3]) {
+    const bool fp32 = c->active_fp32;
+    HQ_HIP(hqk::launch_scalars(c->params(fp32), 0, c->stream));
+    for (int n = 0; n <= c->N; ++n)
+        HQ_HIP(hqk::launch_layer(M_RESID, false, fp32, c->params(fp32), c->layers[n], c->xbuf(fp32), 0, c->stream));
+    HQ_HIP(hqk::launch_scalars(c->params(fp32), 1, c->stream));
+    HQ_HIP(hipMemcpyAsync(misc, c->P64.sc.misc, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HQ_HIP(hipStreamSynchronize(c->stream));
+}
+
+void widen(hq_ctx* c) {
+    std::vector<double> s32(2 * (c->N + 1));
+    // inverse FP32 scales, recomputed on the host
+    for (int n = 0; n <= c->N; ++n) {
+        int e = (int)std::lround(std::log2(binom_d(c->N, n)));
+        s32[n] = std::ldexp(1.0, -e);
+    }
+    uint32_t begin = 0;
+    for (int n = 0; n <= c->N; ++n) {
+        const uint32_t cnt = (uint32_t)binom_d(c->N, n);
+        HQ_HIP(hqk::launch_widen(c->x32, c->x64, begin, cnt, s32[n], c->stream));
+        begin += cnt;
+    }
+    c->active_fp32 = false;
+}
+
+double max_delta(hq_ctx* c) {
+    std::vector<double> d(c->N + 1);
+    HQ_HIP(hipMemcpyAsync(d.data(), c->P64.sc.delta, (c->N + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HQ_HIP(hipStreamSynchronize(c->stream));
+    double m = 0.0;
+    for (int n = 1; n < c->N; ++n) m = std::max(m, d[n]);
+    return m;
+}
+
+hq_status solve_impl(hq_ctx* c, double tol, hq_info* info) {
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HQ_ERR_INVALID_ARG, "tol must be finite and > 0");
+    hq_info inf{};
+    auto t0 = std::chrono::steady_clock::now();
+    if (c->lam_zero) {
+        c->have_iterate = true;
+        inf.status = HQ_OK;
+        if (info) *info = inf;
+        return HQ_OK;
+    }
+    const int max_iters = c->opts.max_iters > 0 ? c->opts.max_iters : 100000;
+    const int fixed = c->opts.check_every;
+    const bool delta_stop = c->opts.stop == HQ_STOP_DELTA;
+    const int prec = c->opts.precision;
+    hq_status status = HQ_ERR_NOT_CONVERGED;
+    double sweep_ms = 0.0;
+    try {
+        run_init(c, prec != HQ_FP64);
+        int k = 0, next = fixed > 0 ? fixed : std::min(8, max_iters);
+        double last_res = -1.0, prev_res = -1.0;
+        int prev_k = 0, stall = 0, fp64_from = prec == HQ_FP64 ? 0 : -1;
+        double misc[3] = {0, 0, 0};
+        while (k < max_iters) {
+            HQ_HIP(hipEventRecord(c->ev0, c->stream));
+            const int todo = delta_stop ? 1 : std::max(1, std::min(next, max_iters) - k);
+            for (int i = 0; i < todo; ++i) run_sweep(c, delta_stop);
+            HQ_HIP(hipEventRecord(c->ev1, c->stream));
+            k += todo;
+            if (delta_stop) {
+                HQ_HIP(hipEventSynchronize(c->ev1));
+                float ms = 0.f;
+                HQ_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                sweep_ms += ms;
+                const double d = max_delta(c);
+                if (d <= tol || k >= max_iters) {
+                    run_residual(c, misc);
+                    inf.checks++;
+                    last_res = misc[0];
+                    if (misc[2] != 0.0) status = HQ_ERR_NUMERIC;
+                    else status = (d <= tol) ? HQ_OK : HQ_ERR_NOT_CONVERGED;
+                    break;
+                }
+                continue;
+            }
+            run_residual(c, misc);
+            float ms = 0.f;
+            HQ_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+            sweep_ms += ms;
+            inf.checks++;
+            const double res = misc[0];
+            if (misc[2] != 0.0 || !std::isfinite(res)) {
+                status = HQ_ERR_NUMERIC;
+                last_res = res;
+                break;
+            }
+            prev_res = last_res;
+            last_res = res;
+            if (res <= tol) {
+                status = HQ_OK;
+                break;
+            }
+            // FP32 storage floor: hand over to FP64 (polish form) or stop
+            if (c->active_fp32) {
+                const bool stalled = prev_res > 0.0 && res > 0.8 * prev_res;
+                if (res <= 1e-6 || stalled) {
+                    if (prec == HQ_FP32_POLISH64) {
+                        widen(c);
+                        fp64_from = k;
+                        prev_res = -1.0;
+                        last_res = -1.0;
+                        next = k + (fixed > 0 ? fixed : 4);
+                        prev_k = k;
+                        continue;
+                    }
+                    if (stalled && ++stall >= 3) {
+                        status = HQ_ERR_NOT_CONVERGED;
+                        break;
+                    }
+                }
+            }
+            // schedule the next check: extrapolate the geometric decay
+            if (fixed > 0) {
+                next = k + fixed;
+            } else if (prev_res > 0.0 && res < prev_res) {
+                const double rate = std::pow(res / prev_res, 1.0 / std::max(1, k - prev_k));
+                const double need = std::log(tol / res) / std::log(rate);
+                int step = (int)std::ceil(need);
+                step = std::max(1, std::min(step, 64));
+                next = k + step;
+            } else {
+                next = k + 8;
+            }
+            prev_k = k;
+        }
+        inf.iterations = k;
+        inf.fp64_iterations = fp64_from >= 0 ? k - fp64_from : 0;
+        inf.residual = last_res;
+        HQ_HIP(hqk::launch_scalars(c->params(c->active_fp32), 0, c->stream));
+        std::vector<double> scal(8 * (c->N + 1) + 8);
+        HQ_HIP(hipMemcpyAsync(scal.data(), c->d_scal, scal.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HQ_HIP(hipStreamSynchronize(c->stream));
+        const int L = c->N + 1;
+        inf.mass_error = scal[7 * L + 1] - 1.0;
+        double drift = 0.0;
+        for (int n = 0; n < c->N; ++n) drift = std::max(drift, std::fabs(scal[n] / c->Lam - 1.0));
+        inf.max_layer_drift = drift;
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    inf.seconds = std::chrono::duration<double>(t1 - t0).count();
+    inf.sweep_seconds = sweep_ms * 1e-3;
+    inf.state_updates_per_s = inf.sweep_seconds > 0 ? (double)(c->states() - 2) * inf.iterations / inf.sweep_seconds : 0.0;
+    inf.status = status;
+    if (info) *info = inf;
+    if (status == HQ_ERR_NOT_CONVERGED) g_err = "max_iters reached (or FP32 floor) before tol";
+    if (status == HQ_ERR_NUMERIC) g_err = "non-finite value or zero denominator in a layer reduction";
+    return status;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// C ABI
+// ----------------------------------------------------------------------------
+extern "C" {
+
+void hq_default_options(hq_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = HQ_FP64;
+    o->inner = HQ_INNER_CLOSED;
+    o->init = HQ_INIT_UNIFORM;
+    o->stop = HQ_STOP_RESIDUAL;
+    o->max_iters = 100000;
+    o->check_every = 0;
+    o->tile_bits = 0;
+    o->device = -1;
+}
+
+const char* hq_last_error(void) { return g_err.c_str(); }
+
+hq_status hq_create(int N, int J, const double* lambda_j, const double* mu_i, const int32_t* pref_lists,
+                    const hq_options* opts, hq_ctx** out) {
+    if (!out) return fail(HQ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    try {
+        return create_impl(N, J, lambda_j, mu_i, pref_lists, opts, out);
+    } catch (const std::bad_alloc&) {
+        return fail(HQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    } catch (...) {
+        return fail(HQ_ERR_DEVICE, "unexpected failure in hq_create");
+    }
+}
+
+void hq_destroy(hq_ctx* ctx) { delete ctx; }
+
+hq_status hq_solve(hq_ctx* ctx, double tol, hq_info* info) {
+    if (!ctx) return fail(HQ_ERR_INVALID_ARG, "ctx is NULL");
+    try {
+        return solve_impl(ctx, tol, info);
+    } catch (const std::bad_alloc&) {
+        return fail(HQ_ERR_OUT_OF_MEMORY, "allocation failed");
+    } catch (...) {
+        return fail(HQ_ERR_DEVICE, "unexpected failure in hq_solve");
+    }
+}
+
+hq_status hq_iterate(hq_ctx* ctx, int iters) {
+    if (!ctx) return fail(HQ_ERR_INVALID_ARG, "ctx is NULL");
+    if (iters < 0) return fail(HQ_ERR_INVALID_ARG, "iters must be >= 0");
+    if (ctx->lam_zero) {
+        ctx->have_iterate = true;
+        return HQ_OK;
+    }
+    try {
+        if (!ctx->have_iterate) run_init(ctx, ctx->opts.precision != HQ_FP64);
+        for (int i = 0; i < iters; ++i) run_sweep(ctx, false);
+        HQ_HIP(hipStreamSynchronize(ctx->stream));
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    return HQ_OK;
+}
+
+hq_status hq_reset(hq_ctx* ctx) {
+    if (!ctx) return fail(HQ_ERR_INVALID_ARG, "ctx is NULL");
+    if (ctx->lam_zero) return HQ_OK;
+    try {
+        run_init(ctx, ctx->opts.precision != HQ_FP64);
+        HQ_HIP(hipStreamSynchronize(ctx->stream));
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    return HQ_OK;
+}
+
+hq_status hq_residual(hq_ctx* ctx, double* residual) {
+    if (!ctx || !residual) return fail(HQ_ERR_INVALID_ARG, "null argument");
+    if (!ctx->have_iterate) return fail(HQ_ERR_STATE, "no iterate yet");
+    if (ctx->lam_zero) {
+        *residual = 0.0;
+        return HQ_OK;
+    }
+    try {
+        double misc[3];
+        run_residual(ctx, misc);
+        *residual = misc[0];
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    return HQ_OK;
+}
+
+static hq_status export_impl(const hq_ctx* cc, double* dev_out, int conditional, hipStream_t s) {
+    hq_ctx* c = const_cast<hq_ctx*>(cc);
+    const bool fp32 = c->active_fp32;
+    HQ_HIP(hqk::launch_scalars(c->params(fp32), 0, s));
+    for (int n = 0; n <= c->N; ++n)
+        HQ_HIP(hqk::launch_export(fp32, c->params(fp32), c->layers[n], c->xbuf(fp32), dev_out, c->d_orig_bit,
+                                  conditional, s));
+    return HQ_OK;
+}
+
+static hq_status host_export(const hq_ctx* c, double* out, int conditional) {
+    if (!c || !out) return fail(HQ_ERR_INVALID_ARG, "null argument");
+    if (!c->have_iterate) return fail(HQ_ERR_STATE, "no solve has run");
+    const uint64_t S = c->states();
+    if (c->lam_zero) {
+        std::fill(out, out + S, 0.0);
+        out[0] = 1.0;
+        return HQ_OK;
+    }
+    double* tmp = nullptr;
+    try {
+        tmp = dalloc<double>(S);
+        export_impl(c, tmp, conditional, c->stream);
+        HQ_HIP(hipMemcpyAsync(out, tmp, S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HQ_HIP(hipStreamSynchronize(c->stream));
+    } catch (const std::bad_alloc&) {
+        return fail(HQ_ERR_OUT_OF_MEMORY, "device allocation failed");
+    } catch (const HipError& e) {
+        if (tmp) (void)hipFree(tmp);
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    (void)hipFree(tmp);
+    return HQ_OK;
+}
+
+hq_status hq_state(const hq_ctx* ctx, double* P) { return host_export(ctx, P, 0); }
+hq_status hq_conditional(const hq_ctx* ctx, double* pcond) { return host_export(ctx, pcond, 1); }
+
+hq_status hq_state_device(const hq_ctx* ctx, double* dev_P, void* stream) {
+    if (!ctx || !dev_P) return fail(HQ_ERR_INVALID_ARG, "null argument");
+    if (!ctx->have_iterate) return fail(HQ_ERR_STATE, "no solve has run");
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    try {
+        if (ctx->lam_zero) {
+            HQ_HIP(hipMemsetAsync(dev_P, 0, ctx->states() * sizeof(double), s));
+            const double one = 1.0;
+            HQ_HIP(hipMemcpyAsync(dev_P, &one, sizeof(double), hipMemcpyHostToDevice, s));
+            HQ_HIP(hipStreamSynchronize(s));
+            return HQ_OK;
+        }
+        if (s != ctx->stream) HQ_HIP(hipStreamSynchronize(ctx->stream));
+        export_impl(ctx, dev_P, 0, s);
+        // on the library's own stream the caller cannot order after it: finish here
+        if (!stream) HQ_HIP(hipStreamSynchronize(s));
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    return HQ_OK;
+}
+
+hq_status hq_marginals(const hq_ctx* cc, double* rho_u, double* p_n) {
+    if (!cc) return fail(HQ_ERR_INVALID_ARG, "ctx is NULL");
+    if (!cc->have_iterate) return fail(HQ_ERR_STATE, "no solve has run");
+    hq_ctx* c = const_cast<hq_ctx*>(cc);
+    const int N = c->N;
+    if (c->lam_zero) {
+        if (rho_u) std::fill(rho_u, rho_u + N, 0.0);
+        if (p_n) {
+            std::fill(p_n, p_n + N + 1, 0.0);
+            p_n[0] = 1.0;
+        }
+        return HQ_OK;
+    }
+    try {
+        const bool fp32 = c->active_fp32;
+        HQ_HIP(hqk::launch_scalars(c->params(fp32), 0, c->stream));
+        HQ_HIP(hipMemsetAsync(c->d_rho, 0, 32 * sizeof(double), c->stream));
+        for (int n = 0; n <= N; ++n)
+            HQ_HIP(hqk::launch_marginal(fp32, c->params(fp32), c->layers[n], c->xbuf(fp32), c->d_part, c->d_rho,
+                                        c->stream));
+        std::vector<double> rho(32), scal(8 * (N + 1) + 8);
+        HQ_HIP(hipMemcpyAsync(rho.data(), c->d_rho, 32 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HQ_HIP(hipMemcpyAsync(scal.data(), c->d_scal, scal.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HQ_HIP(hipStreamSynchronize(c->stream));
+        if (rho_u)
+            for (int u = 0; u < N; ++u) rho_u[c->orig[u]] = rho[u];
+        if (p_n) {
+            const int L = N + 1;
+            const double mass = scal[7 * L + 1];
+            for (int n = 0; n <= N; ++n) {
+                const double layer_sum = (n == N) ? 1.0 : scal[n] / c->Lam;
+                p_n[n] = scal[3 * L + n] * layer_sum / mass;
+            }
+        }
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    return HQ_OK;
+}
+
+hq_status hq_layer_scalars(const hq_ctx* cc, double* out) {
+    if (!cc || !out) return fail(HQ_ERR_INVALID_ARG, "null argument");
+    if (!cc->have_iterate) return fail(HQ_ERR_STATE, "no iterate yet");
+    hq_ctx* c = const_cast<hq_ctx*>(cc);
+    const int N = c->N, L = N + 1;
+    if (c->lam_zero) {
+        std::fill(out, out + 4 * L, 0.0);
+        out[2] = 1.0;
+        return HQ_OK;
+    }
+    try {
+        HQ_HIP(hqk::launch_scalars(c->params(c->active_fp32), 0, c->stream));
+        std::vector<double> scal(8 * L + 8);
+        HQ_HIP(hipMemcpyAsync(scal.data(), c->d_scal, scal.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HQ_HIP(hipStreamSynchronize(c->stream));
+        for (int n = 0; n <= N; ++n) {
+            out[4 * n + 0] = scal[0 * L + n];
+            out[4 * n + 1] = scal[1 * L + n];
+            out[4 * n + 2] = scal[3 * L + n];
+            out[4 * n + 3] = scal[2 * L + n];
+        }
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    return HQ_OK;
+}
+
+int hq_num_units(const hq_ctx* ctx) { return ctx ? ctx->N : 0; }
+
+hq_status hq_solve_batch(hq_ctx* const* ctxs, int count, double tol, hq_info* infos) {
+    if (count < 0 || (count > 0 && !ctxs)) return fail(HQ_ERR_INVALID_ARG, "bad batch arguments");
+    hq_status worst = HQ_OK;
+    for (int i = 0; i < count; ++i) {
+        if (!ctxs[i]) return fail(HQ_ERR_INVALID_ARG, "null context in batch");
+        hq_info inf{};
+        hq_status s = hq_solve(ctxs[i], tol, &inf);
+        if (infos) infos[i] = inf;
+        if (s != HQ_OK && worst == HQ_OK) worst = s;
+    }
+    return worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Bars (written per test): FP64 state — L1 <= 1e-10 on converged P and
+relative 1e-11 per entry at a fixed iteration count; FP32 state — L1 <= 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpu, exact
+from paper_2603_03019_amd import hq
+from paper_2603_03019_amd.instances import Instance, config_instance, make_instance
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    cpu.build(force=False)
+    hq.load()
+
+
+def _gpu(inst, **kw):
+    return hq.create_from_instance(inst, **kw)
+
+
+def _rel_close(a, b, rtol):
+    scale = np.maximum(np.abs(a), np.abs(b))
+    bad = np.abs(a - b) > rtol * scale + 1e-300
+    return int(bad.sum())
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3])
+def test_small_fp64_converged_matches_oracle_and_dense(idx):
+    inst = config_instance(1, idx)  # N=10, J=40, load 0.5
+    say(f"case C1 idx={idx}")
+    ctx = _gpu(inst)
+    info = hq.hq_solve(ctx, 1e-12)
+    P = hq.hq_state(ctx)
+    ref = cpu.solve(inst, tol=1e-12)
+    assert info["residual"] <= 1e-12
+    assert np.abs(P - ref.P).sum() <= 1e-10
+    assert np.abs(P - exact.dense_solve(inst)).sum() <= 1e-10
+    assert abs(info["iterations"] - ref.iterations) <= 1
+
+
+@pytest.mark.parametrize("inner", ["closed", "one"])
+@pytest.mark.parametrize("N,J,b,cfg", [(10, 40, 0, 1), (12, 60, 4, 2), (14, 120, 6, 3), (15, 90, 10, 2),
+                                       (13, 50, 12, 2), (16, 200, 8, 3)])
+def test_iteration_path_matches_oracle(N, J, b, cfg, inner):
+    """Same iterate after k outer iterations (Gauss-Seidel across layers,
+    the same inner reading), entry by entry, for several tile widths."""
+    inst = config_instance(cfg, 11, N=N, J=J)
+    say(f"case path N={N} J={J} b={b} inner={inner}")
+    ctx = _gpu(inst, inner=hq.HQ_INNER_ONE if inner == "one" else hq.HQ_INNER_CLOSED, tile_bits=b)
+    done = 0
+    for k in (1, 2, 5):
+        hq.hq_iterate(ctx, k - done)
+        done = k
+        got = hq.hq_conditional(ctx)
+        ref = cpu.solve(inst, tol=0.0, max_iters=k, inner=inner)
+        assert _rel_close(got, ref.pcond, 1e-11) == 0, f"k={k}"
+        sc = hq.hq_layer_scalars(ctx)
+        np.testing.assert_allclose(sc[:, 0], ref.lam_n, rtol=1e-12)
+        np.testing.assert_allclose(sc[:, 1], ref.mu_n, rtol=1e-12)
+    hq.hq_destroy(ctx)
+
+
+@pytest.mark.parametrize("load", [0.3, 0.9])
+def test_medium_fp64_converged(load):
+    inst = config_instance(2, 1, N=16, J=200, load=load)
+    say(f"case N=16 load={load}")
+    ctx = _gpu(inst)
+    info = hq.hq_solve(ctx, 1e-12)
+    ref = cpu.solve(inst, tol=1e-12)
+    P = hq.hq_state(ctx)
+    assert np.abs(P - ref.P).sum() <= 1e-10
+    rho, pn = hq.hq_marginals(ctx)
+    rr, rp = cpu.marginals(inst.N, ref.P)
+    np.testing.assert_allclose(rho, rr, rtol=1e-9, atol=1e-13)
+    np.testing.assert_allclose(pn, rp, rtol=1e-9, atol=1e-15)
+    assert abs(info["mass_error"]) < 1e-9
+
+
+def test_edge_sizes():
+    # N = 1: P(busy) = Lambda / (Lambda + nu)
+    inst = Instance(1, 2, np.array([0.4, 0.6]), np.array([1.5]), np.array([[0], [0]], np.int32),
+                    np.zeros((1, 2)), np.zeros((2, 2)), 1.0)
+    say("case N=1")
+    ctx = _gpu(inst)
+    hq.hq_solve(ctx, 1e-14)
+    P = hq.hq_state(ctx)
+    assert P[1] == pytest.approx(1.0 / 2.5, abs=1e-15)
+    # N = 2 hand example
+    inst2 = Instance(2, 2, np.array([1.0, 2.0]), np.array([1.0, 3.0]), np.array([[0, 1], [1, 0]], np.int32),
+                     np.zeros((2, 2)), np.zeros((2, 2)), 0.75)
+    say("case N=2")
+    ctx2 = _gpu(inst2)
+    hq.hq_solve(ctx2, 1e-14)
+    np.testing.assert_allclose(hq.hq_state(ctx2), np.array([30, 39, 17, 42]) / 128.0, atol=1e-14)
+    # single demand node, ordered hunting with equal rates
+    inst3 = make_instance(9, 1, config=901, index=0, load=0.8, homogeneous=True)
+    say("case J=1")
+    ctx3 = _gpu(inst3)
+    hq.hq_solve(ctx3, 1e-13)
+    rho, _ = hq.hq_marginals(ctx3)
+    np.testing.assert_allclose(rho, exact.ordered_hunting_rho(inst3.pref[0], 9, inst3.Lambda), rtol=1e-9)
+
+
+def test_zero_arrivals():
+    inst = config_instance(1, 0)
+    inst.lam = np.zeros_like(inst.lam)
+    say("case Lambda=0")
+    ctx = _gpu(inst)
+    info = hq.hq_solve(ctx, 1e-10)
+    P = hq.hq_state(ctx)
+    assert P[0] == 1.0 and P[1:].sum() == 0.0 and info["iterations"] == 0
+
+
+def test_homogeneous_erlang_on_gpu():
+    inst = config_instance(2, 0, N=16, J=100, homogeneous=True, load=0.6)
+    say("case Erlang N=16")
+    ctx = _gpu(inst)
+    hq.hq_solve(ctx, 1e-12)
+    _, pn = hq.hq_marginals(ctx)
+    np.testing.assert_allclose(pn, exact.erlang_marginal(16, inst.Lambda), rtol=1e-9, atol=1e-15)
+
+
+def test_fp32_form_error_against_oracle():
+    inst = config_instance(2, 2, N=18, J=200, load=0.6)
+    ref = cpu.solve(inst, tol=1e-12)
+    say("case FP32 N=18")
+    ctx = _gpu(inst, precision=hq.HQ_FP32, max_iters=4000)
+    info = hq.hq_solve(ctx, 1e-7, allow_not_converged=True)
+    P = hq.hq_state(ctx)
+    l1 = np.abs(P - ref.P).sum()
+    say(f"  FP32 residual {info['residual']:.3e} L1 {l1:.3e}")
+    assert l1 <= 1e-6
+    say("case FP32+polish N=18")
+    ctx2 = _gpu(inst, precision=hq.HQ_FP32_POLISH64)
+    info2 = hq.hq_solve(ctx2, 1e-12)
+    assert info2["fp64_iterations"] > 0
+    assert np.abs(hq.hq_state(ctx2) - ref.P).sum() <= 1e-10
+
+
+def test_not_converged_and_resume():
+    inst = config_instance(2, 3, N=14, J=100)
+    say("case max_iters / resume")
+    ctx = _gpu(inst, max_iters=3, check_every=1)
+    with pytest.raises(hq.HQError) as e:
+        hq.hq_solve(ctx, 1e-12)
+    assert e.value.status == hq.HQ_ERR_NOT_CONVERGED
+    snap = hq.hq_conditional(ctx)  # iterate stays readable
+    # resuming from the exported iterate reproduces the uninterrupted run bitwise
+    a = _gpu(inst)
+    hq.hq_iterate(a, 3 + 4)
+    b = _gpu(inst, init_state=snap)
+    hq.hq_iterate(b, 4)
+    assert np.array_equal(hq.hq_conditional(a), hq.hq_conditional(b))
+
+
+def test_deterministic_results():
+    inst = config_instance(3, 4, N=16, J=300)
+    say("case determinism")
+    ctx = _gpu(inst)
+    hq.hq_solve(ctx, 1e-10)
+    P1 = hq.hq_state(ctx)
+    hq.hq_solve(ctx, 1e-10)
+    P2 = hq.hq_state(ctx)
+    assert np.array_equal(P1, P2)
+
+
+def test_paper_delta_stop_on_gpu():
+    inst = config_instance(1, 5)
+    say("case delta stop")
+    ctx = _gpu(inst, stop=hq.HQ_STOP_DELTA)
+    info = hq.hq_solve(ctx, 1e-12)
+    ref = cpu.solve(inst, tol=1e-12, stop="delta")
+    assert abs(info["iterations"] - ref.iterations) <= 1
+    assert np.abs(hq.hq_state(ctx) - ref.P).sum() <= 1e-9
+
+
+def test_state_device_export_to_torch():
+    import torch
+
+    inst = config_instance(1, 6)
+    say("case device export")
+    ctx = _gpu(inst)
+    hq.hq_solve(ctx, 1e-12)
+    out = torch.empty(1 << inst.N, dtype=torch.float64, device="cuda")
+    hq.hq_state_device(ctx, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), hq.hq_state(ctx))
