@@ -80,6 +80,9 @@ typedef struct {
     int check_every;          /* residual cadence; <= 0: adaptive (predicts the crossing) */
     int tile_bits;            /* low bits per tile b (4..12); <= 0: choose */
     int device;               /* HIP device ordinal; < 0: current device */
+    int stored_layers;        /* top layers whose dispatch coefficients are precomputed and
+                                 stored (FP64, N values per state): 0 = choose (at most
+                                 2^N/32 states), < 0 = none, k > 0 = layers N-k..N-1 */
     const double* init_rho;   /* [N] per-unit utilisations for HQ_INIT_PRODUCT (copied) */
     const double* init_state; /* [2^N] conditional probabilities for HQ_INIT_STATE (copied) */
     void* stream;             /* hipStream_t to run on (e.g. torch's current stream); NULL = own stream */

@@ -27,6 +27,7 @@ hipError_t launch_marginal(bool fp32, const SweepParams& P, const LayerArgs& A, 
                            double* rho, hipStream_t s);
 hipError_t launch_widen(const float* src, double* dst, uint32_t begin, uint32_t count, double factor,
                         hipStream_t s);
+hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, uint32_t nnodes, hipStream_t s);
 }  // namespace hqk
 
 namespace {
@@ -94,8 +95,10 @@ struct hq_ctx {
     float* x32 = nullptr;
     double *d_nu = nullptr, *d_mu_lo = nullptr, *d_tcoef = nullptr, *d_scal = nullptr, *d_part = nullptr;
     double *d_scale64 = nullptr, *d_scale32 = nullptr, *d_rho = nullptr, *d_xu = nullptr, *d_given = nullptr;
-    uint32_t *d_binom = nullptr, *d_layer_off = nullptr, *d_lo_qstart = nullptr, *d_root_off = nullptr,
-             *d_root_list = nullptr, *d_orig_bit = nullptr;
+    uint32_t *d_binom = nullptr, *d_layer_off = nullptr, *d_lo_qstart = nullptr, *d_ent_off = nullptr,
+             *d_ent_list = nullptr, *d_orig_bit = nullptr, *d_seg_desc = nullptr, *d_segoff = nullptr;
+    double* d_coefs = nullptr;
+    int stored_from = -1;  // first layer with stored coefficients (-1: none)
     uint16_t *d_lo_unrank = nullptr, *d_lo_rank = nullptr;
     TrieNode* d_nodes = nullptr;
     unsigned int* d_counters = nullptr;
@@ -106,10 +109,10 @@ struct hq_ctx {
 
     ~hq_ctx() { release(); }
     void release() {
-        void* ptrs[] = {x64,      x32,        d_nu,        d_mu_lo,    d_tcoef,   d_scal,      d_part,
-                        d_scale64, d_scale32, d_rho,       d_xu,       d_given,   d_binom,     d_layer_off,
-                        d_lo_qstart, d_root_off, d_root_list, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
-                        d_counters};
+        void* ptrs[] = {x64,       x32,        d_nu,       d_mu_lo,    d_tcoef,     d_scal,     d_part,
+                        d_scale64, d_scale32,  d_rho,      d_xu,       d_given,     d_binom,    d_layer_off,
+                        d_lo_qstart, d_ent_off, d_ent_list, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
+                        d_counters, d_seg_desc, d_segoff,   d_coefs};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         x64 = nullptr;
@@ -219,20 +222,22 @@ std::vector<TrieNode> build_trie(int N, int J, const double* lam, const std::vec
 
 // Per-tile part of the dispatch walk.  For tile T (high units busy iff
 // their bit is set), walk the trie through busy high units: their rates are
-// uniform over the tile's states (tcoef[T][u]).  A low unit ends the uniform
-// walk: its rate is credited per lane iff the unit is busy (tcoef[T][l]),
-// and the subtrees below it become per-lane roots.
+// uniform over the tile's states (tcoef[T][u]).  A low unit l ends the
+// uniform walk: its rate is credited per lane iff l is busy (tcoef[T][l]),
+// and the node (an "entry") is listed under l so that its subtree is walked
+// per lane, and skipped outright when no lane has l busy.
 void build_tiles(int N, int b, const std::vector<TrieNode>& nodes, std::vector<double>& tcoef,
-                 std::vector<uint32_t>& root_off, std::vector<uint32_t>& roots) {
+                 std::vector<uint32_t>& ent_off, std::vector<uint32_t>& ents) {
     const int H = N - b;
     const uint32_t tiles = 1u << H;
     tcoef.assign((size_t)tiles * N, 0.0);
-    root_off.assign((size_t)tiles + 1, 0);
-    roots.clear();
+    ent_off.assign((size_t)tiles * b + 1, 0);
+    ents.clear();
     const uint32_t nn = (uint32_t)nodes.size();
+    std::vector<std::vector<uint32_t>> group(b);
     for (uint32_t T = 0; T < tiles; ++T) {
         double* tc = tcoef.data() + (size_t)T * N;
-        root_off[T] = (uint32_t)roots.size();
+        for (auto& g : group) g.clear();
         const uint32_t Tabs = T << b;
         uint32_t i = 0;
         while (i < nn) {
@@ -248,12 +253,19 @@ void build_tiles(int N, int b, const std::vector<TrieNode>& nodes, std::vector<d
                 }
             } else {
                 tc[u] += nd.rate;
-                for (uint32_t c = i + 1; c < sk; c = nodes[c].skip_unit >> 5) roots.push_back(c);
+                if (sk > i + 1) group[u].push_back(i);
                 i = sk;
             }
         }
+        for (int l = 0; l < b; ++l) {
+            ent_off[(size_t)T * b + l] = (uint32_t)(ents.size() / 2);
+            for (uint32_t e : group[l]) {
+                ents.push_back(e + 1);                        // first child
+                ents.push_back(nodes[e].skip_unit >> 5);      // end of the subtree
+            }
+        }
     }
-    root_off[tiles] = (uint32_t)roots.size();
+    ent_off[(size_t)tiles * b] = (uint32_t)(ents.size() / 2);
 }
 
 void setup_params(hq_ctx* c) {
@@ -270,9 +282,12 @@ void setup_params(hq_ctx* c) {
     P.lo_qstart = c->d_lo_qstart;
     P.mu_lo = c->d_mu_lo;
     P.tcoef = c->d_tcoef;
-    P.root_off = c->d_root_off;
-    P.root_list = c->d_root_list;
+    P.seg_desc = c->d_seg_desc;
+    P.segoff = c->d_segoff;
+    P.ent_off = c->d_ent_off;
+    P.ent_range = reinterpret_cast<const uint2*>(c->d_ent_list);
     P.nodes = c->d_nodes;
+    P.coefs = c->d_coefs;
     const int L = c->N + 1;
     P.sc.lam = c->d_scal + 0 * L;
     P.sc.mu = c->d_scal + 1 * L;
@@ -347,8 +362,8 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
 
     c->nodes = build_trie(N, J, lam, rp);
     std::vector<double> tcoef;
-    std::vector<uint32_t> root_off, roots;
-    build_tiles(N, b, c->nodes, tcoef, root_off, roots);
+    std::vector<uint32_t> ent_off, ents;
+    build_tiles(N, b, c->nodes, tcoef, ent_off, ents);
 
     // layout tables
     std::vector<uint32_t> tb(32 * 32, 0);
@@ -373,25 +388,65 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     for (uint32_t L = 0; L < lo; ++L)
         for (int u = 0; u < b; ++u)
             if ((L >> u) & 1u) mu_lo[L] += c->nu[u];
-    // per-layer segment tables
+    // Segment tables.  segoff[q * 2^H + T]: absolute position of segment
+    // (T, q) = colex rank offset of its high part (sum over the i-th set bit
+    // of T at position b + k of C(b + k, q + i)) plus the layer start.
+    // seg_desc: per layer, one (T << 4 | q) per work-group, in memory order.
+    const int H = c->H;
+    const uint32_t tiles = 1u << H;
+    std::vector<uint32_t> segoff((size_t)(b + 1) * tiles, 0);
+    for (uint32_t T = 0; T < tiles; ++T) {
+        const int h = __builtin_popcount(T);
+        for (int q = 0; q <= b; ++q) {
+            uint32_t off = 0;
+            int i = 0;
+            for (int k = 0; k < H; ++k)
+                if ((T >> k) & 1u) off += (uint32_t)binom_d(b + k, q + (++i));
+            segoff[(size_t)q * tiles + T] = layer_off[h + q] + off;
+        }
+    }
+    std::vector<uint32_t> seg_desc;
     c->layers.resize(N + 1);
     size_t max_groups = 1;
     for (int n = 0; n <= N; ++n) {
         LayerArgs A{};
         A.n = n;
-        A.qlo = std::max(0, n - c->H);
-        A.qhi = std::min(b, n);
-        uint32_t acc = 0;
-        for (int q = A.qlo; q <= A.qhi; ++q) {
-            A.seg_start[q - A.qlo] = acc;
-            acc += (uint32_t)binom_d(c->H, n - q);
+        A.desc_base = (uint32_t)seg_desc.size();
+        for (uint32_t T = 0; T < tiles; ++T) {
+            const int q = n - __builtin_popcount(T);
+            if (q >= 0 && q <= b) seg_desc.push_back((T << 4) | (uint32_t)q);
         }
-        A.seg_start[A.qhi - A.qlo + 1] = acc;
-        A.groups = acc;
-        max_groups = std::max(max_groups, (size_t)acc);
+        A.groups = (uint32_t)seg_desc.size() - A.desc_base;
+        A.count = (uint32_t)binom_d(N, n);
+        max_groups = std::max(max_groups, (size_t)A.groups);
         c->layers[n] = A;
     }
     c->max_groups = max_groups;
+    // Layers near the top (nearly all units busy) have long per-lane walks;
+    // their coefficients are computed once and stored (unit-major).  Auto:
+    // the top layers while they hold at most 2^N / 32 states.
+    int top = o.stored_layers;
+    if (top == 0) {
+        uint64_t acc = 0;
+        top = 0;
+        for (int n = N - 1; n >= 1; --n) {
+            acc += (uint64_t)binom_d(N, n);
+            if (acc > (1ull << N) / 32) break;
+            ++top;
+        }
+    } else if (top < 0) {
+        top = 0;
+    }
+    top = std::min(top, std::max(N - 1, 0));
+    unsigned long long coef_total = 0;
+    c->stored_from = top > 0 ? N - top : -1;
+    for (int n = 1; n <= N - 1; ++n) {
+        if (top > 0 && n >= N - top) {
+            c->layers[n].stored = 1;
+            c->layers[n].coef_base = coef_total;
+            coef_total += (unsigned long long)N * c->layers[n].count;
+        }
+    }
     // storage scales: 1 for FP64; for FP32 the power of two nearest C(N, n)
     std::vector<double> s64(2 * (N + 1), 1.0), s32(2 * (N + 1));
     for (int n = 0; n <= N; ++n) {
@@ -428,8 +483,11 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->d_binom = dalloc<uint32_t>(tb.size());
         c->d_layer_off = dalloc<uint32_t>(layer_off.size());
         c->d_lo_qstart = dalloc<uint32_t>(lo_qstart.size());
-        c->d_root_off = dalloc<uint32_t>(root_off.size());
-        c->d_root_list = dalloc<uint32_t>(roots.size());
+        c->d_ent_off = dalloc<uint32_t>(ent_off.size());
+        c->d_ent_list = dalloc<uint32_t>(ents.size());
+        c->d_seg_desc = dalloc<uint32_t>(seg_desc.size());
+        c->d_segoff = dalloc<uint32_t>(segoff.size());
+        c->d_coefs = dalloc<double>(coef_total);
         c->d_orig_bit = dalloc<uint32_t>(N);
         c->d_lo_unrank = dalloc<uint16_t>(lo_unrank.size());
         c->d_lo_rank = dalloc<uint16_t>(lo_rank.size());
@@ -444,8 +502,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         h2d(c->d_binom, tb, s);
         h2d(c->d_layer_off, layer_off, s);
         h2d(c->d_lo_qstart, lo_qstart, s);
-        h2d(c->d_root_off, root_off, s);
-        h2d(c->d_root_list, roots, s);
+        h2d(c->d_ent_off, ent_off, s);
+        h2d(c->d_ent_list, ents, s);
+        h2d(c->d_seg_desc, seg_desc, s);
+        h2d(c->d_segoff, segoff, s);
         h2d(c->d_orig_bit, orig_bit, s);
         h2d(c->d_lo_unrank, lo_unrank, s);
         h2d(c->d_lo_rank, lo_rank, s);
@@ -456,13 +516,16 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
             c->d_given = dalloc<double>(S);
             HQ_HIP(hipMemcpyAsync(c->d_given, c->state_init.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
         }
+        setup_params(c.get());
+        for (int n = 1; n <= N - 1; ++n)
+            if (c->layers[n].stored)
+                HQ_HIP(hqk::launch_coef(c->P64, c->layers[n], c->d_coefs, (uint32_t)c->nodes.size(), s));
         HQ_HIP(hipStreamSynchronize(s));
     } catch (const std::bad_alloc&) {
         return fail(HQ_ERR_OUT_OF_MEMORY, "device allocation failed");
     } catch (const HipError& e) {
         return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
     }
-    setup_params(c.get());
     *out = c.release();
     return HQ_OK;
 }

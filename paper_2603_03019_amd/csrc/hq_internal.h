@@ -8,7 +8,11 @@
 #define HQ_MAXB 12          // largest low-bit tile width b
 #define HQ_MAXH 26          // largest high-bit count H = N - b
 #define HQ_WG 256           // threads per work-group of the layer kernels
-#define HQ_NPART 3          // partial sums per work-group
+#define HQ_NPART 3          // partial sums per work-group of the layer kernels
+#ifndef HQ_HCHUNK
+#define HQ_HCHUNK 16        // independent high-unit neighbour loads issued together
+#endif
+#define HQ_GRID 2048        // persistent work-groups per layer launch (8 per CU)
 
 // One node of the merged preference trie, in preorder.  A node stands for
 // a preference prefix shared by one or more demand nodes; `rate` is the
@@ -51,24 +55,27 @@ struct SweepParams {
     const uint32_t* lo_qstart;   // [b+2] start of popcount class q in lo_unrank
     const double* mu_lo;         // [2^b] service-rate sum of a low pattern
     const double* tcoef;         // [2^H * N] per-tile dispatch coefficients
-    const uint32_t* root_off;    // [2^H + 1] per-tile list of per-lane trie roots
-    const uint32_t* root_list;
+    const uint32_t* seg_desc;    // per layer and work-group: (T << 4) | q
+    const uint32_t* segoff;      // [(b+1) * 2^H] absolute start of segment (T, q)
+    const uint32_t* ent_off;     // [2^H * b + 1] per tile, per low unit: trie entries below it
+    const uint2* ent_range;      // per entry: the node range [first child, end of subtree)
     const TrieNode* nodes;
+    const double* coefs;         // stored coefficients of the top layers (unit-major per layer)
     const double* scale;         // [N+1] storage scale of each layer (x = scale * p)
     const double* inv_scale;     // [N+1]
     DevScalars sc;
-    double* partials;            // [max_groups * HQ_NPART]
+    double* partials;            // [max_groups * 32]
     unsigned int* counters;      // [N+1]
 };
 
-// Segments of one layer: popcount class q of the low bits and the rank of
-// the high-bit tile among tiles with n - q set bits.
+// Per-layer launch arguments.
 struct LayerArgs {
     int n;
-    int qlo, qhi;
-    uint32_t seg_start[HQ_MAXB + 2];  // prefix over q = qlo..qhi of C(H, n - q)
-    uint32_t groups;                  // total work-groups
-    double beta;                      // unused placeholder (computed on device)
-    double e_n;                       // product-form normaliser for init
+    uint32_t groups;       // work-groups (segments) of the layer
+    uint32_t desc_base;    // first entry of this layer in seg_desc
+    uint32_t count;        // C(N, n)
+    int stored;            // coefficients of this layer are stored in coefs
+    unsigned long long coef_base;  // offset of this layer in coefs (unit-major, count per unit)
+    double e_n;            // product-form normaliser for init
     int init_mode;
 };

@@ -28,45 +28,44 @@
 
 namespace hq {
 
+// Read-only tables are read through the constant address space: uniform
+// indices then become scalar loads (they are never written while a kernel
+// that reads them runs).
+#define HQ_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const HQ_CONST T* ro(const T* p) {
+    return (const HQ_CONST T*)p;
+}
+
 enum Mode { M_PASS1 = 0, M_WRITE = 1, M_RESID = 2 };
 
 __device__ __forceinline__ uint32_t C(const uint32_t* tb, int n, int k) {
     return (k < 0 || k > n) ? 0u : tb[n * 32 + k];
 }
 
-// Colex rank offset of the high part of a state: the sum over the i-th set
-// bit of T (i = 1, 2, ...), at absolute position b + k, of C(b + k, q + i).
-// Adding the colex rank of the low part gives the rank inside the layer.
-__device__ __forceinline__ uint32_t tile_off(const uint32_t* tb, int b, uint32_t Tb, int q) {
-    uint32_t off = 0;
-    int i = 0;
-    while (Tb) {
-        const int k = __ffs(Tb) - 1;
-        Tb &= Tb - 1;
-        ++i;
-        off += C(tb, b + k, q + i);
-    }
-    return off;
+// Work-groups are persistent: a fixed grid walks the layer's segment list.
+// The hardware deals work-groups to the 8 XCDs round-robin; segment j of
+// work-group w is chosen so that each XCD sweeps one contiguous eighth of
+// the list (memory order), which keeps neighbouring tiles in one L2.
+struct SegIter {
+    uint32_t begin, end, step;
+};
+__device__ __forceinline__ SegIter seg_iter(uint32_t groups) {
+    const uint32_t G = gridDim.x, w = blockIdx.x;
+    if (G < 64 || (G & 7u)) return SegIter{w, groups, G};
+    const uint32_t x = w & 7u, per = (groups + 7u) >> 3;
+    const uint32_t lo = x * per, hi = min(groups, lo + per);
+    return SegIter{lo + (w >> 3), hi, G >> 3};
 }
 
-// Work-group -> (q, T): segments are ordered by q, then by the colex rank of
-// T among the (n - q)-subsets of the H high bits.
-__device__ __forceinline__ void decode_segment(const SweepParams& P, const LayerArgs& A, uint32_t g,
-                                               int& q, uint32_t& Tb) {
-    int qi = 0;
-    while (A.qlo + qi < A.qhi && g >= A.seg_start[qi + 1]) ++qi;
-    q = A.qlo + qi;
-    uint32_t r = g - A.seg_start[qi];
-    const int h = A.n - q;
-    Tb = 0;
-    int top = P.H;
-    for (int i = h; i >= 1; --i) {
-        int c = top - 1;
-        while (C(P.binom, c, i) > r) --c;
-        Tb |= 1u << c;
-        r -= C(P.binom, c, i);
-        top = c;
-    }
+// Segment: popcount class q of the low bits and tile T.
+struct Seg {
+    int q;
+    uint32_t Tb;
+};
+__device__ __forceinline__ Seg seg_at(const SweepParams& P, const LayerArgs& A, uint32_t s) {
+    const uint32_t d = ro(P.seg_desc)[A.desc_base + s];
+    return Seg{(int)(d & 15u), d >> 4};
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -78,22 +77,11 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-__device__ __forceinline__ void store_partial(double* p, double v) {
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __double_as_longlong(v),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_partial(const double* p) {
-    return __longlong_as_double(__hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-
-// Reduce three per-thread values over the work-group, publish one partial,
-// and return true in the last work-group of the grid with the grid totals
-// in out[0..2] (sum, sum, max), summed in a fixed order.
-__device__ bool grid_reduce3(double a0, double a1, double a2, double* partials,
-                             unsigned int* counter, double out[3]) {
+// Reduce three per-thread values over the work-group (sum, sum, max) and
+// store them as this work-group's partial.  No fence: the finalize kernel
+// that reads the partials runs after this kernel on the same stream.
+__device__ void block_partial3(double a0, double a1, double a2, double* partials) {
     __shared__ double s_red[3][HQ_WG / 64];
-    __shared__ unsigned s_last;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
@@ -112,26 +100,26 @@ __device__ bool grid_reduce3(double a0, double a1, double a2, double* partials,
             b2 = fmax(b2, s_red[2][i]);
         }
         double* pp = partials + (size_t)blockIdx.x * HQ_NPART;
-        store_partial(pp + 0, b0);
-        store_partial(pp + 1, b1);
-        store_partial(pp + 2, b2);
-        const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == gridDim.x - 1) ? 1u : 0u;
+        pp[0] = b0;
+        pp[1] = b1;
+        pp[2] = b2;
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Fixed-order sum of `count` partial triples by one work-group.
+__device__ void sum_partials3(const double* partials, uint32_t count, double out[3]) {
+    __shared__ double s_red[3][HQ_WG / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-    for (uint32_t i = tid; i < gridDim.x; i += HQ_WG) {
+    for (uint32_t i = tid; i < count; i += HQ_WG) {
         const double* pp = partials + (size_t)i * HQ_NPART;
-        c0 += load_partial(pp + 0);
-        c1 += load_partial(pp + 1);
-        c2 = fmax(c2, load_partial(pp + 2));
+        c0 += pp[0];
+        c1 += pp[1];
+        c2 = fmax(c2, pp[2]);
     }
     c0 = wave_sum(c0);
     c1 = wave_sum(c1);
     c2 = wave_max(c2);
-    __syncthreads();
     if (lane == 0) {
         s_red[0][w] = c0;
         s_red[1][w] = c1;
@@ -148,9 +136,7 @@ __device__ bool grid_reduce3(double a0, double a1, double a2, double* partials,
         out[0] = d0;
         out[1] = d1;
         out[2] = d2;
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -162,48 +148,64 @@ __device__ bool grid_reduce3(double a0, double a1, double a2, double* partials,
 //   M_RESID  balance residual of (1) for the states of layer n.
 // with U~(m) = sum_{u in m} a(m,u) p_{n-1}(m\u) / (Lambda + mu_m) and
 //      D~(m) = sum_{u notin m} nu_u p_{n+1}(m+u) / (Lambda + mu_m).
+// STORED: the layer's coefficients a(m, u) are read from `coefs` instead
+// of being evaluated from the per-tile tables and the trie.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, bool TRACK_DELTA>
+// Per-segment values staged in registers one segment ahead (prefetch).
+struct SegStage {
+    uint32_t off;  // thread k < H: neighbour segment of high unit k; H..H+2: (T,q-1), (T,q+1), (T,q)
+    double cf;     // thread k < H: coefficient of high unit k; 64 + l: entry rate of low unit l
+};
+
+template <bool STORED>
+__device__ __forceinline__ SegStage stage_segment(const SweepParams& P, int n, const Seg& sg) {
+    const int tid = threadIdx.x, b = P.b, H = P.H, N = P.N;
+    const uint32_t tiles = 1u << H;
+    const int q = sg.q;
+    const uint32_t Tb = sg.Tb;
+    SegStage st{0u, 0.0};
+    if (tid < H) {
+        const uint32_t bit = 1u << tid;
+        if (Tb & bit) {
+            st.off = P.segoff[q * tiles + (Tb ^ bit)];
+            st.cf = STORED ? 0.0 : P.tcoef[(size_t)Tb * N + b + tid];
+        } else {
+            st.off = (n < N) ? P.segoff[q * tiles + (Tb | bit)] : 0u;
+            st.cf = P.nu[b + tid];
+        }
+    } else if (tid == H) {
+        st.off = (q >= 1) ? P.segoff[(q - 1) * tiles + Tb] : 0u;
+    } else if (tid == H + 1) {
+        st.off = (q < b && n < N) ? P.segoff[(q + 1) * tiles + Tb] : 0u;
+    } else if (tid == H + 2) {
+        st.off = P.segoff[q * tiles + Tb];
+    }
+    if (tid >= 64 && tid < 64 + b) st.cf = STORED ? 0.0 : P.tcoef[(size_t)Tb * N + (tid - 64)];
+    return st;
+}
+
+template <typename T, int MODE, bool TRACK_DELTA, bool STORED>
 __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
                                                       int inner_one) {
-    __shared__ uint32_t s_offD[HQ_MAXH], s_offU[HQ_MAXH];
-    __shared__ uint32_t s_seg[4];
-    __shared__ uint16_t s_rank[1 << HQ_MAXB];
+    __shared__ uint32_t s_off[HQ_MAXH + 4];      // high unit k: neighbour segment (down if busy, up if idle)
+    __shared__ double s_cf[HQ_MAXH + HQ_MAXB];   // high unit k: a(.,k) if busy else nu_k; low: entry rate
+    __shared__ uint16_t s_rank[1 << HQ_MAXB];    // colex rank of a low pattern inside its class
+    __shared__ uint16_t s_unrank[1 << HQ_MAXB];  // low patterns by (popcount, value)
+    __shared__ uint32_t s_qstart[HQ_MAXB + 2];
+    __shared__ double s_nu[HQ_MAXB];             // service rates of the low units
 
     const int tid = threadIdx.x;
     const int n = A.n, b = P.b, H = P.H, N = P.N;
-    int q;
-    uint32_t Tb;
-    decode_segment(P, A, blockIdx.x, q, Tb);
-
-    if (tid < H) {
-        const uint32_t bit = 1u << tid;
-        if (Tb & bit)
-            s_offD[tid] = P.layer_off[n - 1] + tile_off(P.binom, b, Tb ^ bit, q);
-        else if (n < N)
-            s_offU[tid] = P.layer_off[n + 1] + tile_off(P.binom, b, Tb | bit, q);
-    } else if (tid == H) {
-        s_seg[0] = (q >= 1) ? P.layer_off[n - 1] + tile_off(P.binom, b, Tb, q - 1) : 0u;
-    } else if (tid == H + 1) {
-        s_seg[1] = (q < b && n < N) ? P.layer_off[n + 1] + tile_off(P.binom, b, Tb, q + 1) : 0u;
-    } else if (tid == H + 2) {
-        s_seg[2] = P.layer_off[n] + tile_off(P.binom, b, Tb, q);
+    for (int i = tid; i < (1 << b); i += HQ_WG) {
+        s_rank[i] = P.lo_rank[i];
+        s_unrank[i] = P.lo_unrank[i];
     }
-    for (int i = tid; i < (1 << b); i += HQ_WG) s_rank[i] = P.lo_rank[i];
-    __syncthreads();
+    if (tid <= b + 1) s_qstart[tid] = P.lo_qstart[tid];
+    if (tid >= 32 && tid < 32 + b) s_nu[tid - 32] = P.nu[tid - 32];
 
-    const uint32_t Tabs = Tb << b;
-    double mu_hi = 0.0;
-    for (int k = 0; k < H; ++k)
-        if ((Tb >> k) & 1u) mu_hi += P.nu[b + k];
-    const uint32_t cnt = C(P.binom, b, q);
-    const double* tc = P.tcoef + (size_t)Tb * N;
-    const uint32_t r0 = P.root_off[Tb], r1 = P.root_off[Tb + 1];
     const double is_dn = (n >= 1) ? P.inv_scale[n - 1] : 0.0;
     const double is_up = (n < N) ? P.inv_scale[n + 1] : 0.0;
     const double s_self = P.scale[n], is_self = P.inv_scale[n];
-    const uint32_t offDlo = s_seg[0], offUlo = s_seg[1], offSelf = s_seg[2];
-
     double alpha = 0.0, beta = 0.0, pdn = 0.0, pself = 0.0, pup = 0.0;
     if (MODE == M_PASS1 || MODE == M_WRITE) {
         beta = P.sc.lam[n] / P.sc.mu[n + 1];  // lambda^{k-1}(n) / mu^{k-1}(n+1)
@@ -218,156 +220,268 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
     const uint32_t full = (N >= 32) ? 0xffffffffu : ((1u << N) - 1u);
 
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    for (uint32_t t = tid; t < cnt; t += HQ_WG) {
-        const uint32_t L = P.lo_unrank[P.lo_qstart[q] + t];
-        const uint32_t m = Tabs | L;
-        double U = 0.0, D = 0.0;
-        // high units: segment-aligned, coalesced neighbours
-        for (int k = 0; k < H; ++k) {
-            if ((Tb >> k) & 1u)
-                U += tc[b + k] * (double)x[s_offD[k] + t];
-            else
-                D += P.nu[b + k] * (double)x[s_offU[k] + t];
+    const SegIter it = seg_iter(A.groups);
+    uint32_t si = it.begin;
+    Seg sg{0, 0u};
+    SegStage st{0u, 0.0};
+    if (si < it.end) {
+        sg = seg_at(P, A, si);
+        st = stage_segment<STORED>(P, n, sg);
+    }
+    for (; si < it.end; si += it.step) {
+        const int q = sg.q;
+        const uint32_t Tb = sg.Tb;
+        __syncthreads();  // the previous segment is done with the shared tables
+        if (tid < H + 3) s_off[tid] = st.off;
+        if (tid < H) s_cf[tid] = st.cf;
+        if (tid >= 64 && tid < 64 + b) s_cf[HQ_MAXH + (tid - 64)] = st.cf;
+        __syncthreads();
+        // prefetch the next segment while this one computes
+        const uint32_t sn = si + it.step;
+        if (sn < it.end) {
+            sg = seg_at(P, A, sn);
+            st = stage_segment<STORED>(P, n, sg);
         }
-        // low units: neighbours in segments (T, q -+ 1)
-        for (int l = 0; l < b; ++l) {
-            const uint32_t bit = 1u << l;
-            const bool busy = (L & bit) != 0u;
-            const uint32_t idx = (busy ? offDlo : offUlo) + s_rank[L ^ bit];
-            const double v = (double)x[idx];
-            if (busy)
-                U += tc[l] * v;
-            else
-                D += P.nu[l] * v;
-        }
-        // per-lane remainder of the dispatch walk (subtrees below low units)
-        for (uint32_t r = r0; r < r1; ++r) {
-            uint32_t i = P.root_list[r];
-            const uint32_t end = P.nodes[i].skip_unit >> 5;
-            while (i < end) {
-                const TrieNode nd = P.nodes[i];
-                const bool c = (m & nd.need) == nd.need;
-                if (!__any(c)) {
-                    i = nd.skip_unit >> 5;
-                    continue;
+
+        const uint32_t Tabs = Tb << b;
+        double mu_hi = 0.0;
+        for (int k = 0; k < H; ++k)
+            if ((Tb >> k) & 1u) mu_hi += ro(P.nu)[b + k];
+        const uint32_t cnt = ro(P.binom)[b * 32 + q];
+        const uint32_t offDlo = s_off[H], offUlo = s_off[H + 1], offSelf = s_off[H + 2];
+        const uint32_t rank0 = offSelf - ro(P.layer_off)[n];
+        const HQ_CONST uint32_t* eo = ro(P.ent_off) + (size_t)Tb * b;
+        const double* cs = P.coefs + A.coef_base + rank0;
+        const HQ_CONST double* tcT = ro(P.tcoef) + (size_t)Tb * N;  // this tile's dispatch rates (uniform)
+        const HQ_CONST double* nuc = ro(P.nu);
+        const uint32_t qs = s_qstart[q];
+
+        for (uint32_t t = tid; t < cnt; t += HQ_WG) {
+            const uint32_t L = s_unrank[qs + t];
+            const uint32_t m = Tabs | L;
+            // neighbour values: the low-unit batch, then high units in chunks of
+            // HQ_HCHUNK independent loads
+            double U = 0.0, D = 0.0, mu_lo = 0.0;
+            {
+                double vl[HQ_MAXB];
+#pragma unroll
+                for (int l = 0; l < HQ_MAXB; ++l) {
+                    if (l < b) {
+                        const uint32_t bit = 1u << l;
+                        vl[l] = (double)x[((L & bit) ? offDlo : offUlo) + s_rank[L ^ bit]];
+                    }
                 }
-                if (c) {
-                    const int u = (int)(nd.skip_unit & 31u);
-                    const uint32_t idx = (u >= b) ? s_offD[u - b] + t : offDlo + s_rank[L ^ (1u << u)];
-                    U += nd.rate * (double)x[idx];
+#pragma unroll
+                for (int l = 0; l < HQ_MAXB; ++l) {
+                    if (l < b) {
+                        const double nl = nuc[l];  // uniform: scalar load
+                        if ((L >> l) & 1u) {
+                            const double c = STORED ? cs[(size_t)l * A.count + t] : tcT[l];
+                            U += c * vl[l];
+                            mu_lo += nl;
+                        } else {
+                            D += nl * vl[l];
+                        }
+                    }
                 }
-                ++i;
             }
-        }
-        U *= is_dn;
-        D *= is_up;
-        const double mu_m = mu_hi + P.mu_lo[L];
-        if (MODE == M_RESID) {
-            const double lm = (m == full) ? 0.0 : P.Lam;
-            const double self = (double)x[offSelf + t] * is_self;
-            const double in = pdn * U + pup * D;
-            const double out = pself * self * (lm + mu_m);
-            acc0 += fabs(in - out);
-            acc1 += out;
-        } else {
-            const double inv = 1.0 / (P.Lam + mu_m);
-            const double Ut = U * inv, Dt = D * inv;
-            if (MODE == M_PASS1) {
-                acc0 += Ut;
-                acc1 += mu_m * Dt;
+            for (int k0 = 0; k0 < H; k0 += HQ_HCHUNK) {
+                double vh[HQ_HCHUNK];
+#pragma unroll
+                for (int j = 0; j < HQ_HCHUNK; ++j)
+                    if (k0 + j < H) vh[j] = (double)x[s_off[k0 + j] + t];
+#pragma unroll
+                for (int j = 0; j < HQ_HCHUNK; ++j) {
+                    const int k = k0 + j;
+                    if (k < H) {
+                        if ((Tb >> k) & 1u)
+                            U += (STORED ? cs[(size_t)(b + k) * A.count + t] : tcT[b + k]) * vh[j];
+                        else
+                            D += nuc[b + k] * vh[j];
+                    }
+                }
+            }
+            // per-lane remainder of the dispatch walk: trie subtrees below a busy
+            // low unit whose path through high units is busy in T.  Every index
+            // is wave-uniform (readfirstlane), so node reads are scalar loads.
+            if (!STORED) {
+                for (int l = 0; l < b; ++l) {
+                    const uint32_t e0 = __builtin_amdgcn_readfirstlane(eo[l]);
+                    const uint32_t e1 = __builtin_amdgcn_readfirstlane(eo[l + 1]);
+                    if (e0 == e1 || !__any((L >> l) & 1u)) continue;
+                    for (uint32_t e = e0; e < e1; ++e) {
+                        const HQ_CONST uint32_t* rg =
+                            ro(reinterpret_cast<const uint32_t*>(P.ent_range)) + 2 * (size_t)__builtin_amdgcn_readfirstlane(e);
+                        uint32_t i = rg[0];
+                        const uint32_t end = rg[1];
+                        while (i < end) {
+                            const HQ_CONST TrieNode* nd = ro(P.nodes) + i;
+                            const uint32_t need = nd->need, su = nd->skip_unit;
+                            const bool hit = (m & need) == need;
+                            if (!__any(hit)) {
+                                i = __builtin_amdgcn_readfirstlane(su >> 5);
+                                continue;
+                            }
+                            if (hit) {
+                                const int u = (int)(su & 31u);
+                                const uint32_t idx = (u >= b) ? s_off[u - b] + t : offDlo + s_rank[L ^ (1u << u)];
+                                U += nd->rate * (double)x[idx];
+                            }
+                            i = __builtin_amdgcn_readfirstlane(i + 1);
+                        }
+                    }
+                }
+            }
+            U *= is_dn;
+            D *= is_up;
+            const double mu_m = mu_hi + mu_lo;
+            if (MODE == M_RESID) {
+                const double lm = (m == full) ? 0.0 : P.Lam;
+                const double self = (double)x[offSelf + t] * is_self;
+                const double in = pdn * U + pup * D;
+                const double out = pself * self * (lm + mu_m);
+                acc0 += fabs(in - out);
+                acc1 += out;
             } else {
-                const double p = alpha * Ut + beta * Dt;
-                const uint32_t o = offSelf + t;
-                if (TRACK_DELTA) acc2 = fmax(acc2, fabs(p - (double)x[o] * is_self));
-                const T stored = (T)(p * s_self);
-                x[o] = stored;
-                const double ps = (double)stored * is_self;
-                acc0 += ps;
-                acc1 += mu_m * ps;
+                const double inv = 1.0 / (P.Lam + mu_m);
+                const double Ut = U * inv, Dt = D * inv;
+                if (MODE == M_PASS1) {
+                    acc0 += Ut;
+                    acc1 += mu_m * Dt;
+                } else {
+                    const double p = alpha * Ut + beta * Dt;
+                    const uint32_t o = offSelf + t;
+                    if (TRACK_DELTA) acc2 = fmax(acc2, fabs(p - (double)x[o] * is_self));
+                    const T stored = (T)(p * s_self);
+                    x[o] = stored;
+                    const double ps = (double)stored * is_self;
+                    acc0 += ps;
+                    acc1 += mu_m * ps;
+                }
             }
         }
     }
+    block_partial3(acc0, acc1, acc2, P.partials);
+}
 
+// Layer scalars from the work-group partials of the kernel just run on the
+// same stream (one work-group, fixed summation order).
+__global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode, int n, uint32_t count,
+                                                         int inner_one) {
     double tot[3];
-    if (grid_reduce3(acc0, acc1, acc2, P.partials, P.counters + n, tot) && tid == 0) {
-        double* misc = P.sc.misc;
-        if (MODE == M_PASS1) {
-            // mu* = B / (1 - A) with A = sum mu U~ / lambda(n-1) = 1 - Lambda S_U / lambda(n-1)
-            // (since sum (Lambda + mu_m) U~ = lambda(n-1)), so alpha = mu*/lambda(n-1)
-            // = beta S_muD / (Lambda S_U).
-            const double a = beta * tot[1] / (P.Lam * tot[0]);
-            if (!(tot[0] > 0.0) || !isfinite(a)) misc[2] = 1.0;
-            P.sc.alpha[n] = a;
-        } else if (MODE == M_WRITE) {
-            const double lam = P.Lam * tot[0], mu = tot[1];
-            if (!isfinite(lam) || !(mu > 0.0) || !isfinite(mu)) misc[2] = 1.0;
-            P.sc.lam[n] = lam;
-            P.sc.mu[n] = mu;
-            P.sc.alpha[n] = alpha;
-            P.sc.delta[n] = tot[2];
-        } else {
-            P.sc.rnum[n] = tot[0];
-            P.sc.rden[n] = tot[1];
-            if (!isfinite(tot[0]) || !isfinite(tot[1])) misc[2] = 1.0;
+    sum_partials3(P.partials, count, tot);
+    if (threadIdx.x != 0) return;
+    double* misc = P.sc.misc;
+    const int N = P.N;
+    if (mode == M_PASS1) {
+        // mu* = B / (1 - A) with A = sum mu U~ / lambda(n-1) = 1 - Lambda S_U / lambda(n-1)
+        // (since sum (Lambda + mu_m) U~ = lambda(n-1)), so alpha = mu*/lambda(n-1)
+        // = beta S_muD / (Lambda S_U).
+        const double beta = P.sc.lam[n] / P.sc.mu[n + 1];
+        const double a = beta * tot[1] / (P.Lam * tot[0]);
+        if (!(tot[0] > 0.0) || !isfinite(a)) misc[2] = 1.0;
+        P.sc.alpha[n] = a;
+    } else if (mode == M_WRITE) {
+        const double used = inner_one ? P.sc.mu[n] / P.sc.lam[n - 1] : P.sc.alpha[n];
+        const double lam = P.Lam * tot[0], mu = tot[1];
+        if (!isfinite(lam) || !(mu > 0.0) || !isfinite(mu)) misc[2] = 1.0;
+        P.sc.lam[n] = lam;
+        P.sc.mu[n] = mu;
+        P.sc.alpha[n] = used;
+        P.sc.delta[n] = tot[2];
+    } else if (mode == M_RESID) {
+        P.sc.rnum[n] = tot[0];
+        P.sc.rden[n] = tot[1];
+        if (!isfinite(tot[0]) || !isfinite(tot[1])) misc[2] = 1.0;
+    } else {  // initial iterate
+        P.sc.lam[n] = (n == N) ? 0.0 : P.Lam * tot[0];
+        P.sc.mu[n] = tot[1];
+        P.sc.alpha[n] = 0.0;
+        P.sc.delta[n] = 0.0;
+    }
+}
+
+// Coefficients a(m, u) of every state of one layer, stored unit-major
+// (coefs[coef_base + u * count + rank]), by the plain trie walk of
+// Algorithm 3's rule: a node credits its rate to its unit iff every unit on
+// its path (itself included) is busy in m.  Run once per instance for the
+// layers whose on-the-fly walk would be long (nearly full states).
+__global__ __launch_bounds__(HQ_WG) void coef_kernel(SweepParams P, LayerArgs A, double* __restrict__ coefs,
+                                                     uint32_t nnodes) {
+    const int tid = threadIdx.x;
+    const int n = A.n, b = P.b, H = P.H, N = P.N;
+    const uint32_t tiles = 1u << H;
+    const SegIter it = seg_iter(A.groups);
+    for (uint32_t si = it.begin; si < it.end; si += it.step) {
+        const Seg sg = seg_at(P, A, si);
+        const uint32_t rank0 = P.segoff[sg.q * tiles + sg.Tb] - P.layer_off[n];
+        const uint32_t cnt = C(P.binom, b, sg.q);
+        for (uint32_t t = tid; t < cnt; t += HQ_WG) {
+            const uint32_t m = (sg.Tb << b) | P.lo_unrank[P.lo_qstart[sg.q] + t];
+            double* out = coefs + A.coef_base + rank0 + t;
+            for (int u = 0; u < N; ++u) out[(size_t)u * A.count] = 0.0;
+            uint32_t i = 0;
+            while (i < nnodes) {
+                const TrieNode nd = P.nodes[i];
+                if ((m & nd.need) == nd.need) {
+                    out[(size_t)(nd.skip_unit & 31u) * A.count] += nd.rate;
+                    ++i;
+                } else {
+                    i = nd.skip_unit >> 5;
+                }
+            }
         }
     }
 }
 
 // Initial iterate of one layer: uniform 1/C(N,n) (Algorithm 1 step 2),
 // product form prod_{u in m} x_u / e_n(x), or a given state (bitmask order,
-// original unit labels mapped through `orig`).  Reduces lambda(n), mu(n).
+// original unit labels mapped through `orig_bit`).  Partials for lambda(n), mu(n).
 template <typename T>
 __global__ __launch_bounds__(HQ_WG) void init_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
                                                      const double* __restrict__ xu,
                                                      const double* __restrict__ given,
                                                      const uint32_t* __restrict__ orig_bit) {
-    __shared__ uint32_t s_off;
     const int tid = threadIdx.x;
     const int n = A.n, b = P.b, H = P.H, N = P.N;
-    int q;
-    uint32_t Tb;
-    decode_segment(P, A, blockIdx.x, q, Tb);
-    if (tid == 0) s_off = P.layer_off[n] + tile_off(P.binom, b, Tb, q);
-    __syncthreads();
-    const uint32_t Tabs = Tb << b;
-    double mu_hi = 0.0;
-    for (int k = 0; k < H; ++k)
-        if ((Tb >> k) & 1u) mu_hi += P.nu[b + k];
-    const uint32_t cnt = C(P.binom, b, q);
     const double sc_self = P.scale[n], is_self = P.inv_scale[n];
     double acc0 = 0.0, acc1 = 0.0;
-    for (uint32_t t = tid; t < cnt; t += HQ_WG) {
-        const uint32_t L = P.lo_unrank[P.lo_qstart[q] + t];
-        const uint32_t m = Tabs | L;
-        double p;
-        if (n == 0 || n == N) {
-            p = 1.0;
-        } else if (A.init_mode == 1) {
-            double pr = 1.0;
-            for (int u = 0; u < N; ++u)
-                if ((m >> u) & 1u) pr *= xu[u];
-            p = pr / A.e_n;
-        } else if (A.init_mode == 2) {
-            uint32_t mo = 0;
-            for (int u = 0; u < N; ++u)
-                if ((m >> u) & 1u) mo |= orig_bit[u];
-            p = given[mo];
-        } else {
-            p = 1.0 / (double)C(P.binom, N, n);
+    const SegIter it = seg_iter(A.groups);
+    for (uint32_t si = it.begin; si < it.end; si += it.step) {
+        const Seg sg = seg_at(P, A, si);
+        const uint32_t off = P.segoff[sg.q * (1u << H) + sg.Tb];
+        const uint32_t Tabs = sg.Tb << b;
+        double mu_hi = 0.0;
+        for (int k = 0; k < H; ++k)
+            if ((sg.Tb >> k) & 1u) mu_hi += P.nu[b + k];
+        const uint32_t cnt = C(P.binom, b, sg.q);
+        for (uint32_t t = tid; t < cnt; t += HQ_WG) {
+            const uint32_t L = P.lo_unrank[P.lo_qstart[sg.q] + t];
+            const uint32_t m = Tabs | L;
+            double p;
+            if (n == 0 || n == N) {
+                p = 1.0;
+            } else if (A.init_mode == 1) {
+                double pr = 1.0;
+                for (int u = 0; u < N; ++u)
+                    if ((m >> u) & 1u) pr *= xu[u];
+                p = pr / A.e_n;
+            } else if (A.init_mode == 2) {
+                uint32_t mo = 0;
+                for (int u = 0; u < N; ++u)
+                    if ((m >> u) & 1u) mo |= orig_bit[u];
+                p = given[mo];
+            } else {
+                p = 1.0 / (double)A.count;
+            }
+            const T stored = (T)(p * sc_self);
+            x[off + t] = stored;
+            const double ps = (double)stored * is_self;
+            acc0 += ps;
+            acc1 += (mu_hi + P.mu_lo[L]) * ps;
         }
-        const T stored = (T)(p * sc_self);
-        x[s_off + t] = stored;
-        const double ps = (double)stored * is_self;
-        acc0 += ps;
-        acc1 += (mu_hi + P.mu_lo[L]) * ps;
     }
-    double tot[3];
-    if (grid_reduce3(acc0, acc1, 0.0, P.partials, P.counters + n, tot) && tid == 0) {
-        P.sc.lam[n] = (n == N) ? 0.0 : P.Lam * tot[0];
-        P.sc.mu[n] = tot[1];
-        P.sc.alpha[n] = 0.0;
-        P.sc.delta[n] = 0.0;
-    }
+    block_partial3(acc0, acc1, 0.0, P.partials);
 }
 
 // p(n) of (10) from lambda(n), mu(n); total mass sum_m P(m); residual ratio.
@@ -407,92 +521,89 @@ __global__ __launch_bounds__(HQ_WG) void export_kernel(SweepParams P, LayerArgs 
                                                        double* __restrict__ out,
                                                        const uint32_t* __restrict__ orig_bit,
                                                        int conditional) {
-    __shared__ uint32_t s_self;
     const int tid = threadIdx.x;
     const int n = A.n, b = P.b, N = P.N;
-    int q;
-    uint32_t Tb;
-    decode_segment(P, A, blockIdx.x, q, Tb);
-    if (tid == 0) s_self = P.layer_off[n] + tile_off(P.binom, b, Tb, q);
-    __syncthreads();
-    const uint32_t Tabs = Tb << b;
-    uint32_t hi = 0;
-    for (int u = b; u < N; ++u)
-        if ((Tabs >> u) & 1u) hi |= orig_bit[u];
-    const uint32_t cnt = C(P.binom, b, q);
     const double f = conditional ? P.inv_scale[n] : P.sc.pn[n] * P.inv_scale[n] / P.sc.misc[1];
-    for (uint32_t t = tid; t < cnt; t += HQ_WG) {
-        const uint32_t L = P.lo_unrank[P.lo_qstart[q] + t];
-        uint32_t lo = 0;
-        for (int u = 0; u < b; ++u)
-            if ((L >> u) & 1u) lo |= orig_bit[u];
-        out[hi | lo] = (double)x[s_self + t] * f;
+    const SegIter it = seg_iter(A.groups);
+    for (uint32_t si = it.begin; si < it.end; si += it.step) {
+        const Seg sg = seg_at(P, A, si);
+        const uint32_t off = P.segoff[sg.q * (1u << P.H) + sg.Tb];
+        const uint32_t Tabs = sg.Tb << b;
+        uint32_t hi = 0;
+        for (int u = b; u < N; ++u)
+            if ((Tabs >> u) & 1u) hi |= orig_bit[u];
+        const uint32_t cnt = C(P.binom, b, sg.q);
+        for (uint32_t t = tid; t < cnt; t += HQ_WG) {
+            const uint32_t L = P.lo_unrank[P.lo_qstart[sg.q] + t];
+            uint32_t lo = 0;
+            for (int u = 0; u < b; ++u)
+                if ((L >> u) & 1u) lo |= orig_bit[u];
+            out[hi | lo] = (double)x[off + t] * f;
+        }
     }
 }
 
-// Per-unit busy probabilities: partial sums of P(m) over the states of one
-// layer, for every (relabelled) unit; the last work-group sums the
-// partials in fixed order and adds them into rho[0..N-1].
+// Per-unit busy probabilities: each work-group writes the sums of P(m) over
+// its segments for every (relabelled) unit as one partial row of 32.
 template <typename T>
 __global__ __launch_bounds__(HQ_WG) void marginal_kernel(SweepParams P, LayerArgs A, const T* __restrict__ x,
-                                                         double* __restrict__ part, double* __restrict__ rho) {
-    __shared__ uint32_t s_self;
-    __shared__ double s_w[HQ_WG / 64][32];
-    __shared__ unsigned s_last;
+                                                         double* __restrict__ part) {
+    __shared__ double s_w[HQ_WG / 64][HQ_MAXB + 1];
+    __shared__ double s_hi[HQ_MAXH];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int n = A.n, b = P.b, H = P.H, N = P.N;
-    int q;
-    uint32_t Tb;
-    decode_segment(P, A, blockIdx.x, q, Tb);
-    if (tid == 0) s_self = P.layer_off[n] + tile_off(P.binom, b, Tb, q);
-    __syncthreads();
-    const uint32_t cnt = C(P.binom, b, q);
     const double f = P.sc.pn[n] * P.inv_scale[n] / P.sc.misc[1];
-    double acc[HQ_MAXB + 1];
-    for (int i = 0; i <= HQ_MAXB; ++i) acc[i] = 0.0;
-    for (uint32_t t = tid; t < cnt; t += HQ_WG) {
-        const uint32_t L = P.lo_unrank[P.lo_qstart[q] + t];
-        const double v = (double)x[s_self + t] * f;
-        acc[HQ_MAXB] += v;
-        for (int l = 0; l < HQ_MAXB; ++l)
-            if (l < b && ((L >> l) & 1u)) acc[l] += v;
+    if (tid < HQ_MAXH) s_hi[tid] = 0.0;
+    double lo[HQ_MAXB];
+    for (int l = 0; l < HQ_MAXB; ++l) lo[l] = 0.0;
+    const SegIter it = seg_iter(A.groups);
+    for (uint32_t si = it.begin; si < it.end; si += it.step) {
+        const Seg sg = seg_at(P, A, si);
+        const uint32_t off = P.segoff[sg.q * (1u << H) + sg.Tb];
+        const uint32_t cnt = C(P.binom, b, sg.q);
+        double mass = 0.0;
+        for (uint32_t t = tid; t < cnt; t += HQ_WG) {
+            const uint32_t L = P.lo_unrank[P.lo_qstart[sg.q] + t];
+            const double v = (double)x[off + t] * f;
+            mass += v;
+            for (int l = 0; l < HQ_MAXB; ++l)
+                if (l < b && ((L >> l) & 1u)) lo[l] += v;
+        }
+        mass = wave_sum(mass);
+        __syncthreads();
+        if (lane == 0) s_w[w][HQ_MAXB] = mass;
+        __syncthreads();
+        if (tid == 0) {
+            double sm = 0.0;
+            for (int i = 0; i < HQ_WG / 64; ++i) sm += s_w[i][HQ_MAXB];
+            for (int k = 0; k < H; ++k)
+                if ((sg.Tb >> k) & 1u) s_hi[k] += sm;
+        }
     }
-    for (int i = 0; i <= HQ_MAXB; ++i) {
-        const double s = wave_sum(acc[i]);
-        if (lane == 0) s_w[w][i] = s;
+    for (int l = 0; l < HQ_MAXB; ++l) {
+        const double s = wave_sum(lo[l]);
+        if (lane == 0) s_w[w][l] = s;
     }
     __syncthreads();
-    if (tid < 32) {
-        double s = 0.0;
-        if (tid <= HQ_MAXB)
-            for (int i = 0; i < HQ_WG / 64; ++i) s += s_w[i][tid];
-        s_w[0][tid] = s;
-    }
-    __syncthreads();
-    // partial vector of this work-group: low units, then high units (all get the segment mass)
     double* pp = part + (size_t)blockIdx.x * 32;
     if (tid < N) {
-        double v;
+        double v = 0.0;
         if (tid < b)
-            v = s_w[0][tid];
+            for (int i = 0; i < HQ_WG / 64; ++i) v += s_w[i][tid];
         else
-            v = ((Tb >> (tid - b)) & 1u) ? s_w[0][HQ_MAXB] : 0.0;
-        store_partial(pp + tid, v);
+            v = s_hi[tid - b];
+        pp[tid] = v;
     }
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned t = __hip_atomic_fetch_add(P.counters + n, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == gridDim.x - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (tid < N) {
-        double s = 0.0;
-        for (uint32_t i = 0; i < gridDim.x; ++i) s += load_partial(part + (size_t)i * 32 + tid);
-        rho[tid] += s;
-    }
-    if (tid == 0) __hip_atomic_store(P.counters + n, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Adds the fixed-order sum of `count` marginal partial rows into rho[0..N-1].
+__global__ void marginal_finalize_kernel(SweepParams P, const double* __restrict__ part, uint32_t count,
+                                         double* __restrict__ rho) {
+    const int u = threadIdx.x;
+    if (u >= P.N) return;
+    double s = 0.0;
+    for (uint32_t i = 0; i < count; ++i) s += part[(size_t)i * 32 + u];
+    rho[u] += s;
 }
 
 // FP32 -> FP64 conversion of one layer (precision switch of the polish form).
@@ -511,34 +622,57 @@ namespace hqk {
 
 using namespace hq;
 
-template <typename T>
-static hipError_t launch_layer_t(int mode, bool track_delta, const SweepParams& P, const LayerArgs& A, T* x,
-                                 int inner_one, hipStream_t s) {
-    dim3 grid(A.groups), block(HQ_WG);
+// Persistent grid: at most HQ_GRID work-groups, a multiple of 8 when large.
+static uint32_t grid_for(uint32_t groups) {
+    if (groups < 64) return groups;
+    uint32_t g = groups < HQ_GRID ? groups : HQ_GRID;
+    return g & ~7u;
+}
+
+template <typename T, bool STORED>
+static void launch_layer_s(int mode, bool track_delta, const SweepParams& P, const LayerArgs& A, T* x,
+                           int inner_one, hipStream_t s) {
+    dim3 grid(grid_for(A.groups)), block(HQ_WG);
     if (mode == M_PASS1)
-        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
     else if (mode == M_WRITE && track_delta)
-        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, true>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, true, STORED>), grid, block, 0, s, P, A, x, inner_one);
     else if (mode == M_WRITE)
-        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
     else
-        hipLaunchKernelGGL((layer_kernel<T, M_RESID, false>), grid, block, 0, s, P, A, x, inner_one);
-    return hipGetLastError();
+        hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
 }
 
 hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A,
                         void* x, int inner_one, hipStream_t s) {
-    return fp32 ? launch_layer_t<float>(mode, track_delta, P, A, (float*)x, inner_one, s)
-                : launch_layer_t<double>(mode, track_delta, P, A, (double*)x, inner_one, s);
+    if (fp32) {
+        if (A.stored)
+            launch_layer_s<float, true>(mode, track_delta, P, A, (float*)x, inner_one, s);
+        else
+            launch_layer_s<float, false>(mode, track_delta, P, A, (float*)x, inner_one, s);
+    } else {
+        if (A.stored)
+            launch_layer_s<double, true>(mode, track_delta, P, A, (double*)x, inner_one, s);
+        else
+            launch_layer_s<double, false>(mode, track_delta, P, A, (double*)x, inner_one, s);
+    }
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(HQ_WG), 0, s, P, mode, A.n, grid_for(A.groups), inner_one);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, uint32_t nnodes, hipStream_t s) {
+    hipLaunchKernelGGL(coef_kernel, dim3(grid_for(A.groups)), dim3(HQ_WG), 0, s, P, A, coefs, nnodes);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(bool fp32, const SweepParams& P, const LayerArgs& A, void* x, const double* xu,
                        const double* given, const uint32_t* orig_bit, hipStream_t s) {
-    dim3 grid(A.groups), block(HQ_WG);
+    dim3 grid(grid_for(A.groups)), block(HQ_WG);
     if (fp32)
         hipLaunchKernelGGL((init_kernel<float>), grid, block, 0, s, P, A, (float*)x, xu, given, orig_bit);
     else
         hipLaunchKernelGGL((init_kernel<double>), grid, block, 0, s, P, A, (double*)x, xu, given, orig_bit);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(HQ_WG), 0, s, P, 3, A.n, grid_for(A.groups), 0);
     return hipGetLastError();
 }
 
@@ -549,7 +683,7 @@ hipError_t launch_scalars(const SweepParams& P, int want_residual, hipStream_t s
 
 hipError_t launch_export(bool fp32, const SweepParams& P, const LayerArgs& A, const void* x, double* out,
                          const uint32_t* orig_bit, int conditional, hipStream_t s) {
-    dim3 grid(A.groups), block(HQ_WG);
+    dim3 grid(grid_for(A.groups)), block(HQ_WG);
     if (fp32)
         hipLaunchKernelGGL((export_kernel<float>), grid, block, 0, s, P, A, (const float*)x, out, orig_bit,
                            conditional);
@@ -561,11 +695,13 @@ hipError_t launch_export(bool fp32, const SweepParams& P, const LayerArgs& A, co
 
 hipError_t launch_marginal(bool fp32, const SweepParams& P, const LayerArgs& A, const void* x, double* part,
                            double* rho, hipStream_t s) {
-    dim3 grid(A.groups), block(HQ_WG);
+    dim3 grid(grid_for(A.groups)), block(HQ_WG);
     if (fp32)
-        hipLaunchKernelGGL((marginal_kernel<float>), grid, block, 0, s, P, A, (const float*)x, part, rho);
+        hipLaunchKernelGGL((marginal_kernel<float>), grid, block, 0, s, P, A, (const float*)x, part);
     else
-        hipLaunchKernelGGL((marginal_kernel<double>), grid, block, 0, s, P, A, (const double*)x, part, rho);
+        hipLaunchKernelGGL((marginal_kernel<double>), grid, block, 0, s, P, A, (const double*)x, part);
+    hipLaunchKernelGGL(marginal_finalize_kernel, dim3(1), dim3(32), 0, s, P, (const double*)part,
+                       grid_for(A.groups), rho);
     return hipGetLastError();
 }
 

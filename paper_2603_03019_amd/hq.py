@@ -42,7 +42,7 @@ class HQError(RuntimeError):
 class hq_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("inner", ctypes.c_int), ("init", ctypes.c_int),
                 ("stop", ctypes.c_int), ("max_iters", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("tile_bits", ctypes.c_int), ("device", ctypes.c_int),
+                ("tile_bits", ctypes.c_int), ("device", ctypes.c_int), ("stored_layers", ctypes.c_int),
                 ("init_rho", ctypes.POINTER(ctypes.c_double)),
                 ("init_state", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p)]
 

@@ -136,8 +136,9 @@ def test_fp32_form_error_against_oracle():
     inst = config_instance(2, 2, N=18, J=200, load=0.6)
     ref = cpu.solve(inst, tol=1e-12)
     say("case FP32 N=18")
+    # iterate the FP32 form to its storage floor (it stops when the residual stalls)
     ctx = _gpu(inst, precision=hq.HQ_FP32, max_iters=4000)
-    info = hq.hq_solve(ctx, 1e-7, allow_not_converged=True)
+    info = hq.hq_solve(ctx, 1e-10, allow_not_converged=True)
     P = hq.hq_state(ctx)
     l1 = np.abs(P - ref.P).sum()
     say(f"  FP32 residual {info['residual']:.3e} L1 {l1:.3e}")
@@ -197,3 +198,16 @@ def test_state_device_export_to_torch():
     hq.hq_state_device(ctx, out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), hq.hq_state(ctx))
+
+
+@pytest.mark.parametrize("stored", [-1, 3, 13])
+def test_stored_coefficient_layers(stored):
+    """Top layers with precomputed coefficients give the same iterate as the
+    on-the-fly dispatch walk (and as the oracle)."""
+    inst = config_instance(3, 12, N=14, J=300)
+    say(f"case stored_layers={stored}")
+    ctx = _gpu(inst, stored_layers=stored, inner=hq.HQ_INNER_ONE)
+    hq.hq_iterate(ctx, 4)
+    ref = cpu.solve(inst, tol=0.0, max_iters=4, inner="one")
+    assert _rel_close(hq.hq_conditional(ctx), ref.pcond, 1e-11) == 0
+    assert hq.hq_residual(ctx) == pytest.approx(cpu.residual(inst, ref.P), rel=1e-9)
