@@ -14,6 +14,7 @@
 
 #include "hq.h"
 #include "hq_internal.h"
+#include "hq_layout.h"
 
 namespace hqk {
 hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
@@ -365,58 +366,30 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     std::vector<uint32_t> ent_off, ents;
     build_tiles(N, b, c->nodes, tcoef, ent_off, ents);
 
-    // layout tables
+    // layout tables (hq_layout.h)
+    hqlayout::Layout lay;
+    hqlayout::build_layout(N, b, lay);
     std::vector<uint32_t> tb(32 * 32, 0);
     for (int n = 0; n < 32; ++n)
         for (int k = 0; k <= n; ++k) tb[n * 32 + k] = (uint32_t)binom_d(n, k);
-    std::vector<uint32_t> layer_off(N + 2, 0);
-    for (int n = 0; n <= N; ++n) layer_off[n + 1] = layer_off[n] + (uint32_t)binom_d(N, n);
+    const std::vector<uint32_t>& layer_off = lay.layer_off;
     const uint32_t lo = 1u << b;
-    std::vector<uint16_t> lo_unrank, lo_rank(lo);
-    std::vector<uint32_t> lo_qstart(b + 2, 0);
-    for (int q = 0; q <= b; ++q) {
-        lo_qstart[q] = (uint32_t)lo_unrank.size();
-        uint32_t r = 0;
-        for (uint32_t L = 0; L < lo; ++L)
-            if (__builtin_popcount(L) == q) {
-                lo_unrank.push_back((uint16_t)L);
-                lo_rank[L] = (uint16_t)r++;
-            }
-    }
-    lo_qstart[b + 1] = lo;
+    const std::vector<uint16_t>& lo_unrank = lay.lo_unrank;
+    const std::vector<uint16_t>& lo_rank = lay.lo_rank;
+    const std::vector<uint32_t>& lo_qstart = lay.lo_qstart;
     std::vector<double> mu_lo(lo, 0.0);
     for (uint32_t L = 0; L < lo; ++L)
         for (int u = 0; u < b; ++u)
             if ((L >> u) & 1u) mu_lo[L] += c->nu[u];
-    // Segment tables.  segoff[q * 2^H + T]: absolute position of segment
-    // (T, q) = colex rank offset of its high part (sum over the i-th set bit
-    // of T at position b + k of C(b + k, q + i)) plus the layer start.
-    // seg_desc: per layer, one (T << 4 | q) per work-group, in memory order.
-    const int H = c->H;
-    const uint32_t tiles = 1u << H;
-    std::vector<uint32_t> segoff((size_t)(b + 1) * tiles, 0);
-    for (uint32_t T = 0; T < tiles; ++T) {
-        const int h = __builtin_popcount(T);
-        for (int q = 0; q <= b; ++q) {
-            uint32_t off = 0;
-            int i = 0;
-            for (int k = 0; k < H; ++k)
-                if ((T >> k) & 1u) off += (uint32_t)binom_d(b + k, q + (++i));
-            segoff[(size_t)q * tiles + T] = layer_off[h + q] + off;
-        }
-    }
-    std::vector<uint32_t> seg_desc;
+    const std::vector<uint32_t>& segoff = lay.segoff;
+    const std::vector<uint32_t>& seg_desc = lay.seg_desc;
     c->layers.resize(N + 1);
     size_t max_groups = 1;
     for (int n = 0; n <= N; ++n) {
         LayerArgs A{};
         A.n = n;
-        A.desc_base = (uint32_t)seg_desc.size();
-        for (uint32_t T = 0; T < tiles; ++T) {
-            const int q = n - __builtin_popcount(T);
-            if (q >= 0 && q <= b) seg_desc.push_back((T << 4) | (uint32_t)q);
-        }
-        A.groups = (uint32_t)seg_desc.size() - A.desc_base;
+        A.desc_base = lay.desc_base[n];
+        A.groups = lay.desc_base[n + 1] - lay.desc_base[n];
         A.count = (uint32_t)binom_d(N, n);
         max_groups = std::max(max_groups, (size_t)A.groups);
         c->layers[n] = A;

@@ -23,6 +23,7 @@
 // shuffles, one partial per work-group, and a fixed-order sum by the last
 // work-group to finish, which also derives the layer scalars.
 #include "hq_internal.h"
+#include "hq_layout.h"
 
 #include <math.h>
 
@@ -151,57 +152,38 @@ __device__ void sum_partials3(const double* partials, uint32_t count, double out
 // STORED: the layer's coefficients a(m, u) are read from `coefs` instead
 // of being evaluated from the per-tile tables and the trie.
 // ---------------------------------------------------------------------------
-// Per-segment values staged in registers one segment ahead (prefetch).
-struct SegStage {
-    uint32_t off;  // thread k < H: neighbour segment of high unit k; H..H+2: (T,q-1), (T,q+1), (T,q)
-    double cf;     // thread k < H: coefficient of high unit k; 64 + l: entry rate of low unit l
+// Wave-granular segment iteration for the layer kernels: each 64-lane wave
+// owns one segment at a time and walks its own share of the segment list,
+// XCD-chunked like seg_iter.  No block-wide barrier inside the loop.
+struct WaveIter {
+    uint32_t begin, end, step;
 };
-
-template <bool STORED>
-__device__ __forceinline__ SegStage stage_segment(const SweepParams& P, int n, const Seg& sg) {
-    const int tid = threadIdx.x, b = P.b, H = P.H, N = P.N;
-    const uint32_t tiles = 1u << H;
-    const int q = sg.q;
-    const uint32_t Tb = sg.Tb;
-    SegStage st{0u, 0.0};
-    if (tid < H) {
-        const uint32_t bit = 1u << tid;
-        if (Tb & bit) {
-            st.off = P.segoff[q * tiles + (Tb ^ bit)];
-            st.cf = STORED ? 0.0 : P.tcoef[(size_t)Tb * N + b + tid];
-        } else {
-            st.off = (n < N) ? P.segoff[q * tiles + (Tb | bit)] : 0u;
-            st.cf = P.nu[b + tid];
-        }
-    } else if (tid == H) {
-        st.off = (q >= 1) ? P.segoff[(q - 1) * tiles + Tb] : 0u;
-    } else if (tid == H + 1) {
-        st.off = (q < b && n < N) ? P.segoff[(q + 1) * tiles + Tb] : 0u;
-    } else if (tid == H + 2) {
-        st.off = P.segoff[q * tiles + Tb];
-    }
-    if (tid >= 64 && tid < 64 + b) st.cf = STORED ? 0.0 : P.tcoef[(size_t)Tb * N + (tid - 64)];
-    return st;
+__device__ __forceinline__ WaveIter wave_iter(uint32_t groups) {
+    const uint32_t WPG = HQ_WG / 64;
+    const uint32_t G = gridDim.x, w = blockIdx.x;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (G < 64 || (G & 7u)) return WaveIter{w * WPG + wv, groups, G * WPG};
+    const uint32_t x = w & 7u, per = (groups + 7u) >> 3;
+    const uint32_t lo = x * per, hi = min(groups, lo + per);
+    return WaveIter{lo + (w >> 3) * WPG + wv, hi, (G >> 3) * WPG};
 }
 
 template <typename T, int MODE, bool TRACK_DELTA, bool STORED>
 __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
                                                       int inner_one) {
-    __shared__ uint32_t s_off[HQ_MAXH + 4];      // high unit k: neighbour segment (down if busy, up if idle)
-    __shared__ double s_cf[HQ_MAXH + HQ_MAXB];   // high unit k: a(.,k) if busy else nu_k; low: entry rate
     __shared__ uint16_t s_rank[1 << HQ_MAXB];    // colex rank of a low pattern inside its class
     __shared__ uint16_t s_unrank[1 << HQ_MAXB];  // low patterns by (popcount, value)
     __shared__ uint32_t s_qstart[HQ_MAXB + 2];
-    __shared__ double s_nu[HQ_MAXB];             // service rates of the low units
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int n = A.n, b = P.b, H = P.H, N = P.N;
+    const uint32_t tiles = 1u << H;
     for (int i = tid; i < (1 << b); i += HQ_WG) {
         s_rank[i] = P.lo_rank[i];
         s_unrank[i] = P.lo_unrank[i];
     }
     if (tid <= b + 1) s_qstart[tid] = P.lo_qstart[tid];
-    if (tid >= 32 && tid < 32 + b) s_nu[tid - 32] = P.nu[tid - 32];
+    __syncthreads();
 
     const double is_dn = (n >= 1) ? P.inv_scale[n - 1] : 0.0;
     const double is_up = (n < N) ? P.inv_scale[n + 1] : 0.0;
@@ -218,63 +200,52 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
         pup = (n < N) ? P.sc.pn[n + 1] : 0.0;
     }
     const uint32_t full = (N >= 32) ? 0xffffffffu : ((1u << N) - 1u);
+    const HQ_CONST double* nuc = ro(P.nu);
+    const uint32_t layer0 = ro(P.layer_off)[n];
 
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    const SegIter it = seg_iter(A.groups);
-    uint32_t si = it.begin;
-    Seg sg{0, 0u};
-    SegStage st{0u, 0.0};
-    if (si < it.end) {
-        sg = seg_at(P, A, si);
-        st = stage_segment<STORED>(P, n, sg);
-    }
-    for (; si < it.end; si += it.step) {
-        const int q = sg.q;
-        const uint32_t Tb = sg.Tb;
-        __syncthreads();  // the previous segment is done with the shared tables
-        if (tid < H + 3) s_off[tid] = st.off;
-        if (tid < H) s_cf[tid] = st.cf;
-        if (tid >= 64 && tid < 64 + b) s_cf[HQ_MAXH + (tid - 64)] = st.cf;
-        __syncthreads();
-        // prefetch the next segment while this one computes
-        const uint32_t sn = si + it.step;
-        if (sn < it.end) {
-            sg = seg_at(P, A, sn);
-            st = stage_segment<STORED>(P, n, sg);
-        }
-
-        const uint32_t Tabs = Tb << b;
+    const WaveIter it = wave_iter(A.groups);
+    for (uint32_t si = it.begin; si < it.end; si += it.step) {
+        const uint32_t d = ro(P.seg_desc)[A.desc_base + si];
+        const int q = (int)(d & 15u);
+        const uint32_t Tb = d >> 4;
+        // neighbour segments, wave-uniform: (T xor k, q) for high unit k,
+        // (T, q - 1) / (T, q + 1) for low units, and the segment itself
+        uint32_t off[HQ_MAXH];
+#pragma unroll
+        for (int k = 0; k < HQ_MAXH; ++k)
+            if (k < H) off[k] = hqlayout::high_neighbour(ro(P.segoff), tiles, q, Tb, k, 0u);
+        const uint32_t offDlo = hqlayout::low_down_segment(ro(P.segoff), tiles, q, Tb);
+        const uint32_t offUlo = hqlayout::low_up_segment(ro(P.segoff), tiles, q, b, Tb);
+        const uint32_t offSelf = ro(P.segoff)[hqlayout::seg_index(q, Tb, tiles)];
         double mu_hi = 0.0;
         for (int k = 0; k < H; ++k)
-            if ((Tb >> k) & 1u) mu_hi += ro(P.nu)[b + k];
+            if ((Tb >> k) & 1u) mu_hi += nuc[b + k];
         const uint32_t cnt = ro(P.binom)[b * 32 + q];
-        const uint32_t offDlo = s_off[H], offUlo = s_off[H + 1], offSelf = s_off[H + 2];
-        const uint32_t rank0 = offSelf - ro(P.layer_off)[n];
+        const uint32_t rank0 = offSelf - layer0;
         const HQ_CONST uint32_t* eo = ro(P.ent_off) + (size_t)Tb * b;
         const double* cs = P.coefs + A.coef_base + rank0;
-        const HQ_CONST double* tcT = ro(P.tcoef) + (size_t)Tb * N;  // this tile's dispatch rates (uniform)
-        const HQ_CONST double* nuc = ro(P.nu);
+        const HQ_CONST double* tcT = ro(P.tcoef) + (size_t)Tb * N;  // this tile's dispatch rates
         const uint32_t qs = s_qstart[q];
+        const uint32_t Tabs = Tb << b;
 
-        for (uint32_t t = tid; t < cnt; t += HQ_WG) {
+        for (uint32_t t = lane; t < cnt; t += 64) {
             const uint32_t L = s_unrank[qs + t];
             const uint32_t m = Tabs | L;
-            // neighbour values: the low-unit batch, then high units in chunks of
-            // HQ_HCHUNK independent loads
             double U = 0.0, D = 0.0, mu_lo = 0.0;
+            // low units: neighbours in the small segments (T, q -+ 1)
             {
                 double vl[HQ_MAXB];
 #pragma unroll
                 for (int l = 0; l < HQ_MAXB; ++l) {
                     if (l < b) {
-                        const uint32_t bit = 1u << l;
-                        vl[l] = (double)x[((L & bit) ? offDlo : offUlo) + s_rank[L ^ bit]];
+                        vl[l] = (double)x[hqlayout::low_neighbour(L, l, offDlo, offUlo, s_rank)];
                     }
                 }
 #pragma unroll
                 for (int l = 0; l < HQ_MAXB; ++l) {
                     if (l < b) {
-                        const double nl = nuc[l];  // uniform: scalar load
+                        const double nl = nuc[l];
                         if ((L >> l) & 1u) {
                             const double c = STORED ? cs[(size_t)l * A.count + t] : tcT[l];
                             U += c * vl[l];
@@ -285,29 +256,32 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
                     }
                 }
             }
-            for (int k0 = 0; k0 < H; k0 += HQ_HCHUNK) {
-                double vh[HQ_HCHUNK];
+            // high units: segment-aligned coalesced neighbours, HQ_HCHUNK loads in flight
 #pragma unroll
-                for (int j = 0; j < HQ_HCHUNK; ++j)
-                    if (k0 + j < H) vh[j] = (double)x[s_off[k0 + j] + t];
+            for (int k0 = 0; k0 < HQ_MAXH; k0 += HQ_HCHUNK) {
+                if (k0 < H) {
+                    double vh[HQ_HCHUNK];
 #pragma unroll
-                for (int j = 0; j < HQ_HCHUNK; ++j) {
-                    const int k = k0 + j;
-                    if (k < H) {
-                        if ((Tb >> k) & 1u)
-                            U += (STORED ? cs[(size_t)(b + k) * A.count + t] : tcT[b + k]) * vh[j];
-                        else
-                            D += nuc[b + k] * vh[j];
+                    for (int j = 0; j < HQ_HCHUNK; ++j)
+                        if (k0 + j < HQ_MAXH && k0 + j < H) vh[j] = (double)x[off[k0 + j] + t];
+#pragma unroll
+                    for (int j = 0; j < HQ_HCHUNK; ++j) {
+                        const int k = k0 + j;
+                        if (k < HQ_MAXH && k < H) {
+                            if ((Tb >> k) & 1u)
+                                U += (STORED ? cs[(size_t)(b + k) * A.count + t] : tcT[b + k]) * vh[j];
+                            else
+                                D += nuc[b + k] * vh[j];
+                        }
                     }
                 }
             }
             // per-lane remainder of the dispatch walk: trie subtrees below a busy
-            // low unit whose path through high units is busy in T.  Every index
-            // is wave-uniform (readfirstlane), so node reads are scalar loads.
+            // low unit whose path through high units is busy in T.  Indices are
+            // wave-uniform, so node reads are scalar loads.
             if (!STORED) {
                 for (int l = 0; l < b; ++l) {
-                    const uint32_t e0 = __builtin_amdgcn_readfirstlane(eo[l]);
-                    const uint32_t e1 = __builtin_amdgcn_readfirstlane(eo[l + 1]);
+                    const uint32_t e0 = eo[l], e1 = eo[l + 1];
                     if (e0 == e1 || !__any((L >> l) & 1u)) continue;
                     for (uint32_t e = e0; e < e1; ++e) {
                         const HQ_CONST uint32_t* rg =
@@ -324,7 +298,9 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
                             }
                             if (hit) {
                                 const int u = (int)(su & 31u);
-                                const uint32_t idx = (u >= b) ? s_off[u - b] + t : offDlo + s_rank[L ^ (1u << u)];
+                                const uint32_t idx =
+                                    (u >= b) ? hqlayout::high_neighbour(ro(P.segoff), tiles, q, Tb, u - b, t)
+                                             : hqlayout::low_neighbour(L, u, offDlo, offUlo, s_rank);
                                 U += nd->rate * (double)x[idx];
                             }
                             i = __builtin_amdgcn_readfirstlane(i + 1);
@@ -442,21 +418,28 @@ __global__ __launch_bounds__(HQ_WG) void init_kernel(SweepParams P, LayerArgs A,
                                                      const double* __restrict__ xu,
                                                      const double* __restrict__ given,
                                                      const uint32_t* __restrict__ orig_bit) {
-    const int tid = threadIdx.x;
+    // same wave-granular traversal (and so the same summation order of the
+    // layer sums) as the layer kernels: a resumed iterate reproduces the
+    // uninterrupted run bit for bit
+    const int lane = threadIdx.x & 63;
     const int n = A.n, b = P.b, H = P.H, N = P.N;
+    const uint32_t tiles = 1u << H;
     const double sc_self = P.scale[n], is_self = P.inv_scale[n];
     double acc0 = 0.0, acc1 = 0.0;
-    const SegIter it = seg_iter(A.groups);
+    const WaveIter it = wave_iter(A.groups);
     for (uint32_t si = it.begin; si < it.end; si += it.step) {
-        const Seg sg = seg_at(P, A, si);
-        const uint32_t off = P.segoff[sg.q * (1u << H) + sg.Tb];
-        const uint32_t Tabs = sg.Tb << b;
+        const uint32_t d = ro(P.seg_desc)[A.desc_base + si];
+        const int q = (int)(d & 15u);
+        const uint32_t Tb = d >> 4;
+        const uint32_t off = ro(P.segoff)[hqlayout::seg_index(q, Tb, tiles)];
+        const uint32_t Tabs = Tb << b;
         double mu_hi = 0.0;
         for (int k = 0; k < H; ++k)
-            if ((sg.Tb >> k) & 1u) mu_hi += P.nu[b + k];
-        const uint32_t cnt = C(P.binom, b, sg.q);
-        for (uint32_t t = tid; t < cnt; t += HQ_WG) {
-            const uint32_t L = P.lo_unrank[P.lo_qstart[sg.q] + t];
+            if ((Tb >> k) & 1u) mu_hi += ro(P.nu)[b + k];
+        const uint32_t cnt = ro(P.binom)[b * 32 + q];
+        const uint32_t qs = P.lo_qstart[q];
+        for (uint32_t t = lane; t < cnt; t += 64) {
+            const uint32_t L = P.lo_unrank[qs + t];
             const uint32_t m = Tabs | L;
             double p;
             if (n == 0 || n == N) {
@@ -477,8 +460,11 @@ __global__ __launch_bounds__(HQ_WG) void init_kernel(SweepParams P, LayerArgs A,
             const T stored = (T)(p * sc_self);
             x[off + t] = stored;
             const double ps = (double)stored * is_self;
+            double mu_lo = 0.0;
+            for (int l = 0; l < b; ++l)
+                if ((L >> l) & 1u) mu_lo += ro(P.nu)[l];
             acc0 += ps;
-            acc1 += (mu_hi + P.mu_lo[L]) * ps;
+            acc1 += (mu_hi + mu_lo) * ps;
         }
     }
     block_partial3(acc0, acc1, 0.0, P.partials);
