@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <memory>
 #include <new>
 #include <string>
@@ -29,6 +31,8 @@ hipError_t launch_marginal(bool fp32, const SweepParams& P, const LayerArgs& A, 
 hipError_t launch_widen(const float* src, double* dst, uint32_t begin, uint32_t count, double factor,
                         hipStream_t s);
 hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, uint32_t nnodes, hipStream_t s);
+hipError_t launch_batch(bool fp32, int block, const BatchItem* items, BatchOut* outs, int count,
+                        unsigned int* next, int grid, hipStream_t s);
 }  // namespace hqk
 
 namespace {
@@ -507,23 +511,32 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
 // iteration
 // ----------------------------------------------------------------------------
 
-void run_init(hq_ctx* c, bool fp32) {
+// Host part of the initial iterate: product-form weights x_u = rho/(1-rho)
+// (uploaded) and the elementary symmetric polynomials e_n(x) in FP64.
+// Returns the init mode of the kernels (0 uniform, 1 product, 2 given).
+int prepare_init(hq_ctx* c, std::vector<double>& e) {
     const int N = c->N;
-    std::vector<double> e(N + 1, 0.0);
+    e.assign(N + 1, 0.0);
     if (c->opts.init == HQ_INIT_PRODUCT) {
         std::vector<double> xu(N);
         for (int u = 0; u < N; ++u) {
             double r = std::min(std::max(c->rho_init[u], 1e-6), 1.0 - 1e-6);
             xu[u] = r / (1.0 - r);
         }
-        // elementary symmetric polynomials e_n(x) in FP64
         e[0] = 1.0;
         for (int u = 0; u < N; ++u)
             for (int n = u + 1; n >= 1; --n) e[n] += xu[u] * e[n - 1];
         HQ_HIP(hipMemcpyAsync(c->d_xu, xu.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HQ_HIP(hipStreamSynchronize(c->stream));  // xu lives on the stack of this call
+        return 1;
     }
-    const int mode = c->opts.init == HQ_INIT_PRODUCT ? 1 : (c->opts.init == HQ_INIT_STATE ? 2 : 0);
-    for (int n = 0; n <= N; ++n) {
+    return c->opts.init == HQ_INIT_STATE ? 2 : 0;
+}
+
+void run_init(hq_ctx* c, bool fp32) {
+    std::vector<double> e;
+    const int mode = prepare_init(c, e);
+    for (int n = 0; n <= c->N; ++n) {
         LayerArgs A = c->layers[n];
         A.init_mode = mode;
         A.e_n = e[n];
@@ -700,6 +713,237 @@ hq_status solve_impl(hq_ctx* c, double tol, hq_info* info) {
     if (status == HQ_ERR_NOT_CONVERGED) g_err = "max_iters reached (or FP32 floor) before tol";
     if (status == HQ_ERR_NUMERIC) g_err = "non-finite value or zero denominator in a layer reduction";
     return status;
+}
+
+// ----------------------------------------------------------------------------
+// batched solve
+// ----------------------------------------------------------------------------
+
+// Device buffers and captured graphs of the batch launch, per device.
+struct BatchRes {
+    BatchItem* items = nullptr;
+    BatchOut* outs = nullptr;
+    unsigned int* next = nullptr;
+    int cap = 0;
+    hipStream_t stream = nullptr;
+    struct Graph {
+        bool fp32;
+        int block, count, grid;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+};
+std::mutex g_batch_mu;
+std::map<int, BatchRes> g_batch;
+std::map<std::string, int> g_batch_tuned;  // batch signature -> work-group size
+
+BatchRes& batch_res(int device, int count) {
+    BatchRes& r = g_batch[device];
+    if (!r.stream) HQ_HIP(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
+    if (r.cap < count) {
+        for (auto& g : r.graphs) (void)hipGraphExecDestroy(g.exec);
+        r.graphs.clear();
+        if (r.items) (void)hipFree(r.items);
+        if (r.outs) (void)hipFree(r.outs);
+        if (!r.next) r.next = dalloc<unsigned int>(1);
+        r.cap = std::max(count, 64);
+        r.items = dalloc<BatchItem>(r.cap);
+        r.outs = dalloc<BatchOut>(r.cap);
+    }
+    return r;
+}
+
+// One launch of the batch kernel (reset of the work counter + the
+// persistent kernel) as a captured hipGraph, reused for equal shapes.
+void batch_launch(BatchRes& r, bool fp32, int block, int count, int grid) {
+    for (auto& g : r.graphs)
+        if (g.fp32 == fp32 && g.block == block && g.count == count && g.grid == grid) {
+            HQ_HIP(hipGraphLaunch(g.exec, r.stream));
+            return;
+        }
+    hipGraph_t graph = nullptr;
+    HQ_HIP(hipStreamBeginCapture(r.stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hqk::launch_batch(fp32, block, r.items, r.outs, count, r.next, grid, r.stream);
+    hipError_t ce = hipStreamEndCapture(r.stream, &graph);
+    HQ_HIP(le);
+    HQ_HIP(ce);
+    hipGraphExec_t exec = nullptr;
+    HQ_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    r.graphs.push_back({fp32, block, count, grid, exec});
+    HQ_HIP(hipGraphLaunch(exec, r.stream));
+}
+
+int batch_grid(int count) {
+    int cus = 256;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        cus = prop.multiProcessorCount;
+    return std::max(1, std::min(count, cus * 2));
+}
+
+hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& pos, bool fp32, double tol,
+                      hq_info* infos, int device) {
+    const int count = (int)cs.size();
+    std::vector<BatchItem> items(count);
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    // largest instances first: the work queue then balances the tail
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cs[a]->N > cs[b]->N; });
+    for (int j = 0; j < count; ++j) {
+        hq_ctx* c = cs[order[j]];
+        std::vector<double> e;
+        const int mode = prepare_init(c, e);
+        BatchItem& it = items[j];
+        std::memset(&it, 0, sizeof(it));
+        it.P = c->params(fp32);
+        for (int n = 0; n <= c->N; ++n) {
+            it.layers[n] = c->layers[n];
+            it.layers[n].init_mode = mode;
+            it.layers[n].e_n = e[n];
+        }
+        it.x = c->xbuf(fp32);
+        it.inner_one = c->opts.inner == HQ_INNER_ONE ? 1 : 0;
+        it.max_iters = c->opts.max_iters > 0 ? c->opts.max_iters : 100000;
+        it.check_every = c->opts.check_every;
+        it.tol = tol;
+        it.init_mode = mode;
+        it.xu = c->d_xu;
+        it.given = c->d_given;
+        it.orig_bit = c->d_orig_bit;
+    }
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    BatchRes& r = batch_res(device, count);
+    const int grid = batch_grid(count);
+    // autotuner: time each work-group size on this batch (a few iterations)
+    std::string sig = std::string(fp32 ? "f32" : "f64") + ":" + std::to_string(count);
+    {
+        std::vector<int> ns;
+        for (auto* c : cs) ns.push_back(c->N);
+        std::sort(ns.begin(), ns.end());
+        for (int n : ns) sig += "," + std::to_string(n);
+    }
+    int block = 0;
+    auto tuned = g_batch_tuned.find(sig);
+    if (tuned != g_batch_tuned.end()) {
+        block = tuned->second;
+    } else {
+        std::vector<BatchItem> probe = items;
+        for (auto& it : probe) {
+            it.max_iters = std::min(it.max_iters, 6);
+            it.check_every = 6;
+        }
+        HQ_HIP(hipMemcpyAsync(r.items, probe.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, r.stream));
+        hipEvent_t e0, e1;
+        HQ_HIP(hipEventCreate(&e0));
+        HQ_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int bs : {256, 512, 1024}) {
+            batch_launch(r, fp32, bs, count, grid);  // warm-up (graph build)
+            HQ_HIP(hipEventRecord(e0, r.stream));
+            batch_launch(r, fp32, bs, count, grid);
+            HQ_HIP(hipEventRecord(e1, r.stream));
+            HQ_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                block = bs;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        g_batch_tuned[sig] = block;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    HQ_HIP(hipMemcpyAsync(r.items, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, r.stream));
+    hipEvent_t k0, k1;
+    HQ_HIP(hipEventCreate(&k0));
+    HQ_HIP(hipEventCreate(&k1));
+    HQ_HIP(hipEventRecord(k0, r.stream));
+    batch_launch(r, fp32, block, count, grid);
+    HQ_HIP(hipEventRecord(k1, r.stream));
+    std::vector<BatchOut> outs(count);
+    HQ_HIP(hipMemcpyAsync(outs.data(), r.outs, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, r.stream));
+    HQ_HIP(hipStreamSynchronize(r.stream));
+    float kms = 0.f;
+    HQ_HIP(hipEventElapsedTime(&kms, k0, k1));
+    (void)hipEventDestroy(k0);
+    (void)hipEventDestroy(k1);
+    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    hq_status worst = HQ_OK;
+    for (int j = 0; j < count; ++j) {
+        hq_ctx* c = cs[order[j]];
+        c->have_iterate = true;
+        c->active_fp32 = fp32;
+        c->iterations_done = outs[j].iterations;
+        const hq_status st = (hq_status)outs[j].status;
+        if (st != HQ_OK && worst == HQ_OK) worst = st;
+        if (infos) {
+            hq_info& inf = infos[pos[order[j]]];
+            std::memset(&inf, 0, sizeof(inf));
+            inf.status = st;
+            inf.iterations = outs[j].iterations;
+            inf.checks = outs[j].checks;
+            inf.residual = outs[j].residual;
+            inf.seconds = wall;
+            inf.sweep_seconds = kms * 1e-3;
+            inf.state_updates_per_s =
+                kms > 0.f ? (double)(c->states() - 2) * outs[j].iterations / (kms * 1e-3) : 0.0;
+        }
+    }
+    return worst;
+}
+
+hq_status batch_impl(hq_ctx* const* ctxs, int count, double tol, hq_info* infos) {
+    if (count < 0 || (count > 0 && !ctxs)) return fail(HQ_ERR_INVALID_ARG, "bad batch arguments");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HQ_ERR_INVALID_ARG, "tol must be finite and > 0");
+    std::vector<hq_ctx*> g64, g32;
+    std::vector<int> p64, p32;
+    int device = -1;
+    for (int i = 0; i < count; ++i) {
+        hq_ctx* c = ctxs[i];
+        if (!c) return fail(HQ_ERR_INVALID_ARG, "null context in batch");
+        if (device < 0) device = c->device;
+        if (c->device != device) return fail(HQ_ERR_INVALID_ARG, "batch contexts must share one device");
+        if (c->opts.precision == HQ_FP32_POLISH64)
+            return fail(HQ_ERR_INVALID_ARG, "batched solves take HQ_FP64 or HQ_FP32 contexts");
+        if (c->opts.stop != HQ_STOP_RESIDUAL)
+            return fail(HQ_ERR_INVALID_ARG, "batched solves use the residual stopping rule");
+    }
+    hq_status worst = HQ_OK;
+    for (int i = 0; i < count; ++i) {
+        hq_ctx* c = ctxs[i];
+        if (c->lam_zero) {
+            c->have_iterate = true;
+            if (infos) {
+                std::memset(&infos[i], 0, sizeof(hq_info));
+                infos[i].status = HQ_OK;
+            }
+            continue;
+        }
+        HQ_HIP(hipStreamSynchronize(c->stream));
+        if (c->opts.precision == HQ_FP32) {
+            g32.push_back(c);
+            p32.push_back(i);
+        } else {
+            g64.push_back(c);
+            p64.push_back(i);
+        }
+    }
+    if (device >= 0) HQ_HIP(hipSetDevice(device));
+    if (!g64.empty()) {
+        hq_status s = batch_group(g64, p64, false, tol, infos, device);
+        if (s != HQ_OK && worst == HQ_OK) worst = s;
+    }
+    if (!g32.empty()) {
+        hq_status s = batch_group(g32, p32, true, tol, infos, device);
+        if (s != HQ_OK && worst == HQ_OK) worst = s;
+    }
+    if (worst == HQ_ERR_NOT_CONVERGED) g_err = "some instances reached max_iters before tol";
+    if (worst == HQ_ERR_NUMERIC) g_err = "non-finite value in a batched instance";
+    return worst;
 }
 
 }  // namespace
@@ -928,16 +1172,13 @@ hq_status hq_layer_scalars(const hq_ctx* cc, double* out) {
 int hq_num_units(const hq_ctx* ctx) { return ctx ? ctx->N : 0; }
 
 hq_status hq_solve_batch(hq_ctx* const* ctxs, int count, double tol, hq_info* infos) {
-    if (count < 0 || (count > 0 && !ctxs)) return fail(HQ_ERR_INVALID_ARG, "bad batch arguments");
-    hq_status worst = HQ_OK;
-    for (int i = 0; i < count; ++i) {
-        if (!ctxs[i]) return fail(HQ_ERR_INVALID_ARG, "null context in batch");
-        hq_info inf{};
-        hq_status s = hq_solve(ctxs[i], tol, &inf);
-        if (infos) infos[i] = inf;
-        if (s != HQ_OK && worst == HQ_OK) worst = s;
+    try {
+        return batch_impl(ctxs, count, tol, infos);
+    } catch (const std::bad_alloc&) {
+        return fail(HQ_ERR_OUT_OF_MEMORY, "allocation failed in hq_solve_batch");
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
     }
-    return worst;
 }
 
 }  // extern "C"

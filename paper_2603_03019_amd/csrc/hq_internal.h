@@ -79,3 +79,25 @@ struct LayerArgs {
     double e_n;            // product-form normaliser for init
     int init_mode;
 };
+
+// One instance of a batched solve: everything the persistent batch kernel
+// needs to run Algorithm 1 on it inside one work-group.
+struct BatchItem {
+    SweepParams P;
+    LayerArgs layers[31];     // n = 0..N
+    void* x;                  // state vector (FP64 or FP32, as the launch)
+    int inner_one;
+    int max_iters;
+    int check_every;          // <= 0: adaptive
+    double tol;
+    int init_mode;            // 0 uniform, 1 product form, 2 given state
+    const double* xu;         // product-form x_u (relabelled)
+    const double* given;      // given state (original bitmask order)
+    const uint32_t* orig_bit; // relabelled unit -> original bit
+};
+
+// Per-instance results of a batched solve.
+struct BatchOut {
+    int iterations, checks, status, pad;
+    double residual;
+};

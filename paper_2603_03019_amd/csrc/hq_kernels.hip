@@ -29,6 +29,9 @@
 
 namespace hq {
 
+#define HQ_ERR_NOT_CONVERGED_CODE 4
+#define HQ_ERR_NUMERIC_CODE 5
+
 // Read-only tables are read through the constant address space: uniform
 // indices then become scalar loads (they are never written while a kernel
 // that reads them runs).
@@ -168,6 +171,185 @@ __device__ __forceinline__ WaveIter wave_iter(uint32_t groups) {
     return WaveIter{lo + (w >> 3) * WPG + wv, hi, (G >> 3) * WPG};
 }
 
+// Scalars of one layer update, fixed for the whole layer.
+struct ModeScalars {
+    double alpha, beta;       // coefficients of U~ and D~ in (12)
+    double pdn, pself, pup;   // p(n-1), p(n), p(n+1) (residual)
+    double is_dn, is_up;      // inverse storage scales of layers n-1, n+1
+    double s_self, is_self;   // storage scale of layer n and its inverse
+};
+
+template <int MODE>
+__device__ __forceinline__ ModeScalars mode_scalars(const SweepParams& P, int n, int inner_one, const double* lam,
+                                                    const double* mu, const double* alpha_closed,
+                                                    const double* pn) {
+    const int N = P.N;
+    ModeScalars ms{};
+    ms.is_dn = (n >= 1) ? P.inv_scale[n - 1] : 0.0;
+    ms.is_up = (n < N) ? P.inv_scale[n + 1] : 0.0;
+    ms.s_self = P.scale[n];
+    ms.is_self = P.inv_scale[n];
+    if (MODE == M_PASS1 || MODE == M_WRITE) {
+        ms.beta = lam[n] / mu[n + 1];  // lambda^{k-1}(n) / mu^{k-1}(n+1)
+        if (MODE == M_WRITE)
+            ms.alpha = inner_one ? mu[n] / lam[n - 1]  // mu^{k-1}(n) / lambda^k(n-1)
+                                 : alpha_closed[n];    // closed-form limit (first pass)
+    } else {
+        ms.pdn = (n >= 1) ? pn[n - 1] : 0.0;
+        ms.pself = pn[n];
+        ms.pup = (n < N) ? pn[n + 1] : 0.0;
+    }
+    return ms;
+}
+
+// One wave updates (or, for M_RESID / M_PASS1, evaluates) the states of
+// segment `si` of layer A.n; accumulates the layer sums in acc0..acc2.
+template <typename T, int MODE, bool TRACK_DELTA, bool STORED>
+__device__ __forceinline__ void segment_update(const SweepParams& P, const LayerArgs& A, T* __restrict__ x,
+                                               uint32_t si, const uint16_t* s_rank, const uint16_t* s_unrank,
+                                               const uint32_t* s_qstart, const ModeScalars& ms, double& acc0,
+                                               double& acc1, double& acc2) {
+    const int lane = threadIdx.x & 63;
+    const int n = A.n, b = P.b, H = P.H, N = P.N;
+    const uint32_t tiles = 1u << H;
+    const uint32_t full = (N >= 32) ? 0xffffffffu : ((1u << N) - 1u);
+    const HQ_CONST double* nuc = ro(P.nu);
+    const uint32_t layer0 = ro(P.layer_off)[n];
+    const double alpha = ms.alpha, beta = ms.beta, pdn = ms.pdn, pself = ms.pself, pup = ms.pup;
+    const double is_dn = ms.is_dn, is_up = ms.is_up, s_self = ms.s_self, is_self = ms.is_self;
+    const uint32_t d = ro(P.seg_desc)[A.desc_base + si];
+    const int q = (int)(d & 15u);
+    const uint32_t Tb = d >> 4;
+    // neighbour segments, wave-uniform: (T xor k, q) for high unit k,
+    // (T, q - 1) / (T, q + 1) for low units, and the segment itself
+    uint32_t off[HQ_MAXH];
+#pragma unroll
+    for (int k = 0; k < HQ_MAXH; ++k)
+        if (k < H) off[k] = hqlayout::high_neighbour(ro(P.segoff), tiles, q, Tb, k, 0u);
+    const uint32_t offDlo = hqlayout::low_down_segment(ro(P.segoff), tiles, q, Tb);
+    const uint32_t offUlo = hqlayout::low_up_segment(ro(P.segoff), tiles, q, b, Tb);
+    const uint32_t offSelf = ro(P.segoff)[hqlayout::seg_index(q, Tb, tiles)];
+    double mu_hi = 0.0;
+    for (int k = 0; k < H; ++k)
+        if ((Tb >> k) & 1u) mu_hi += nuc[b + k];
+    const uint32_t cnt = ro(P.binom)[b * 32 + q];
+    const uint32_t rank0 = offSelf - layer0;
+    const HQ_CONST uint32_t* eo = ro(P.ent_off) + (size_t)Tb * b;
+    const double* cs = P.coefs + A.coef_base + rank0;
+    const HQ_CONST double* tcT = ro(P.tcoef) + (size_t)Tb * N;  // this tile's dispatch rates
+    const uint32_t qs = s_qstart[q];
+    const uint32_t Tabs = Tb << b;
+
+    for (uint32_t t = lane; t < cnt; t += 64) {
+        const uint32_t L = s_unrank[qs + t];
+        const uint32_t m = Tabs | L;
+        double U = 0.0, D = 0.0, mu_lo = 0.0;
+        // low units: neighbours in the small segments (T, q -+ 1)
+        {
+            double vl[HQ_MAXB];
+#pragma unroll
+            for (int l = 0; l < HQ_MAXB; ++l) {
+                if (l < b) {
+                    vl[l] = (double)x[hqlayout::low_neighbour(L, l, offDlo, offUlo, s_rank)];
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < HQ_MAXB; ++l) {
+                if (l < b) {
+                    const double nl = nuc[l];
+                    if ((L >> l) & 1u) {
+                        const double c = STORED ? cs[(size_t)l * A.count + t] : tcT[l];
+                        U += c * vl[l];
+                        mu_lo += nl;
+                    } else {
+                        D += nl * vl[l];
+                    }
+                }
+            }
+        }
+        // high units: segment-aligned coalesced neighbours, HQ_HCHUNK loads in flight
+#pragma unroll
+        for (int k0 = 0; k0 < HQ_MAXH; k0 += HQ_HCHUNK) {
+            if (k0 < H) {
+                double vh[HQ_HCHUNK];
+#pragma unroll
+                for (int j = 0; j < HQ_HCHUNK; ++j)
+                    if (k0 + j < HQ_MAXH && k0 + j < H) vh[j] = (double)x[off[k0 + j] + t];
+#pragma unroll
+                for (int j = 0; j < HQ_HCHUNK; ++j) {
+                    const int k = k0 + j;
+                    if (k < HQ_MAXH && k < H) {
+                        if ((Tb >> k) & 1u)
+                            U += (STORED ? cs[(size_t)(b + k) * A.count + t] : tcT[b + k]) * vh[j];
+                        else
+                            D += nuc[b + k] * vh[j];
+                    }
+                }
+            }
+        }
+        // per-lane remainder of the dispatch walk: trie subtrees below a busy
+        // low unit whose path through high units is busy in T.  Indices are
+        // wave-uniform, so node reads are scalar loads.
+        if (!STORED) {
+            for (int l = 0; l < b; ++l) {
+                const uint32_t e0 = eo[l], e1 = eo[l + 1];
+                if (e0 == e1 || !__any((L >> l) & 1u)) continue;
+                for (uint32_t e = e0; e < e1; ++e) {
+                    const HQ_CONST uint32_t* rg =
+                        ro(reinterpret_cast<const uint32_t*>(P.ent_range)) + 2 * (size_t)__builtin_amdgcn_readfirstlane(e);
+                    uint32_t i = rg[0];
+                    const uint32_t end = rg[1];
+                    while (i < end) {
+                        const HQ_CONST TrieNode* nd = ro(P.nodes) + i;
+                        const uint32_t need = nd->need, su = nd->skip_unit;
+                        const bool hit = (m & need) == need;
+                        if (!__any(hit)) {
+                            i = __builtin_amdgcn_readfirstlane(su >> 5);
+                            continue;
+                        }
+                        if (hit) {
+                            const int u = (int)(su & 31u);
+                            const uint32_t idx =
+                                (u >= b) ? hqlayout::high_neighbour(ro(P.segoff), tiles, q, Tb, u - b, t)
+                                         : hqlayout::low_neighbour(L, u, offDlo, offUlo, s_rank);
+                            U += nd->rate * (double)x[idx];
+                        }
+                        i = __builtin_amdgcn_readfirstlane(i + 1);
+                    }
+                }
+            }
+        }
+        U *= is_dn;
+        D *= is_up;
+        const double mu_m = mu_hi + mu_lo;
+        if (MODE == M_RESID) {
+            const double lm = (m == full) ? 0.0 : P.Lam;
+            const double self = (double)x[offSelf + t] * is_self;
+            const double in = pdn * U + pup * D;
+            const double out = pself * self * (lm + mu_m);
+            acc0 += fabs(in - out);
+            acc1 += out;
+        } else {
+            const double inv = 1.0 / (P.Lam + mu_m);
+            const double Ut = U * inv, Dt = D * inv;
+            if (MODE == M_PASS1) {
+                acc0 += Ut;
+                acc1 += mu_m * Dt;
+            } else {
+                const double p = alpha * Ut + beta * Dt;
+                const uint32_t o = offSelf + t;
+                if (TRACK_DELTA) acc2 = fmax(acc2, fabs(p - (double)x[o] * is_self));
+                const T stored = (T)(p * s_self);
+                x[o] = stored;
+                const double ps = (double)stored * is_self;
+                acc0 += ps;
+                acc1 += mu_m * ps;
+            }
+        }
+    }
+
+}
+
 template <typename T, int MODE, bool TRACK_DELTA, bool STORED>
 __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
                                                       int inner_one) {
@@ -175,168 +357,19 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
     __shared__ uint16_t s_unrank[1 << HQ_MAXB];  // low patterns by (popcount, value)
     __shared__ uint32_t s_qstart[HQ_MAXB + 2];
 
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int n = A.n, b = P.b, H = P.H, N = P.N;
-    const uint32_t tiles = 1u << H;
+    const int tid = threadIdx.x;
+    const int b = P.b;
     for (int i = tid; i < (1 << b); i += HQ_WG) {
         s_rank[i] = P.lo_rank[i];
         s_unrank[i] = P.lo_unrank[i];
     }
     if (tid <= b + 1) s_qstart[tid] = P.lo_qstart[tid];
     __syncthreads();
-
-    const double is_dn = (n >= 1) ? P.inv_scale[n - 1] : 0.0;
-    const double is_up = (n < N) ? P.inv_scale[n + 1] : 0.0;
-    const double s_self = P.scale[n], is_self = P.inv_scale[n];
-    double alpha = 0.0, beta = 0.0, pdn = 0.0, pself = 0.0, pup = 0.0;
-    if (MODE == M_PASS1 || MODE == M_WRITE) {
-        beta = P.sc.lam[n] / P.sc.mu[n + 1];  // lambda^{k-1}(n) / mu^{k-1}(n+1)
-        if (MODE == M_WRITE)
-            alpha = inner_one ? P.sc.mu[n] / P.sc.lam[n - 1]  // mu^{k-1}(n) / lambda^k(n-1)
-                              : P.sc.alpha[n];                // closed-form limit (first pass)
-    } else {
-        pdn = (n >= 1) ? P.sc.pn[n - 1] : 0.0;
-        pself = P.sc.pn[n];
-        pup = (n < N) ? P.sc.pn[n + 1] : 0.0;
-    }
-    const uint32_t full = (N >= 32) ? 0xffffffffu : ((1u << N) - 1u);
-    const HQ_CONST double* nuc = ro(P.nu);
-    const uint32_t layer0 = ro(P.layer_off)[n];
-
+    const ModeScalars ms = mode_scalars<MODE>(P, A.n, inner_one, P.sc.lam, P.sc.mu, P.sc.alpha, P.sc.pn);
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     const WaveIter it = wave_iter(A.groups);
-    for (uint32_t si = it.begin; si < it.end; si += it.step) {
-        const uint32_t d = ro(P.seg_desc)[A.desc_base + si];
-        const int q = (int)(d & 15u);
-        const uint32_t Tb = d >> 4;
-        // neighbour segments, wave-uniform: (T xor k, q) for high unit k,
-        // (T, q - 1) / (T, q + 1) for low units, and the segment itself
-        uint32_t off[HQ_MAXH];
-#pragma unroll
-        for (int k = 0; k < HQ_MAXH; ++k)
-            if (k < H) off[k] = hqlayout::high_neighbour(ro(P.segoff), tiles, q, Tb, k, 0u);
-        const uint32_t offDlo = hqlayout::low_down_segment(ro(P.segoff), tiles, q, Tb);
-        const uint32_t offUlo = hqlayout::low_up_segment(ro(P.segoff), tiles, q, b, Tb);
-        const uint32_t offSelf = ro(P.segoff)[hqlayout::seg_index(q, Tb, tiles)];
-        double mu_hi = 0.0;
-        for (int k = 0; k < H; ++k)
-            if ((Tb >> k) & 1u) mu_hi += nuc[b + k];
-        const uint32_t cnt = ro(P.binom)[b * 32 + q];
-        const uint32_t rank0 = offSelf - layer0;
-        const HQ_CONST uint32_t* eo = ro(P.ent_off) + (size_t)Tb * b;
-        const double* cs = P.coefs + A.coef_base + rank0;
-        const HQ_CONST double* tcT = ro(P.tcoef) + (size_t)Tb * N;  // this tile's dispatch rates
-        const uint32_t qs = s_qstart[q];
-        const uint32_t Tabs = Tb << b;
-
-        for (uint32_t t = lane; t < cnt; t += 64) {
-            const uint32_t L = s_unrank[qs + t];
-            const uint32_t m = Tabs | L;
-            double U = 0.0, D = 0.0, mu_lo = 0.0;
-            // low units: neighbours in the small segments (T, q -+ 1)
-            {
-                double vl[HQ_MAXB];
-#pragma unroll
-                for (int l = 0; l < HQ_MAXB; ++l) {
-                    if (l < b) {
-                        vl[l] = (double)x[hqlayout::low_neighbour(L, l, offDlo, offUlo, s_rank)];
-                    }
-                }
-#pragma unroll
-                for (int l = 0; l < HQ_MAXB; ++l) {
-                    if (l < b) {
-                        const double nl = nuc[l];
-                        if ((L >> l) & 1u) {
-                            const double c = STORED ? cs[(size_t)l * A.count + t] : tcT[l];
-                            U += c * vl[l];
-                            mu_lo += nl;
-                        } else {
-                            D += nl * vl[l];
-                        }
-                    }
-                }
-            }
-            // high units: segment-aligned coalesced neighbours, HQ_HCHUNK loads in flight
-#pragma unroll
-            for (int k0 = 0; k0 < HQ_MAXH; k0 += HQ_HCHUNK) {
-                if (k0 < H) {
-                    double vh[HQ_HCHUNK];
-#pragma unroll
-                    for (int j = 0; j < HQ_HCHUNK; ++j)
-                        if (k0 + j < HQ_MAXH && k0 + j < H) vh[j] = (double)x[off[k0 + j] + t];
-#pragma unroll
-                    for (int j = 0; j < HQ_HCHUNK; ++j) {
-                        const int k = k0 + j;
-                        if (k < HQ_MAXH && k < H) {
-                            if ((Tb >> k) & 1u)
-                                U += (STORED ? cs[(size_t)(b + k) * A.count + t] : tcT[b + k]) * vh[j];
-                            else
-                                D += nuc[b + k] * vh[j];
-                        }
-                    }
-                }
-            }
-            // per-lane remainder of the dispatch walk: trie subtrees below a busy
-            // low unit whose path through high units is busy in T.  Indices are
-            // wave-uniform, so node reads are scalar loads.
-            if (!STORED) {
-                for (int l = 0; l < b; ++l) {
-                    const uint32_t e0 = eo[l], e1 = eo[l + 1];
-                    if (e0 == e1 || !__any((L >> l) & 1u)) continue;
-                    for (uint32_t e = e0; e < e1; ++e) {
-                        const HQ_CONST uint32_t* rg =
-                            ro(reinterpret_cast<const uint32_t*>(P.ent_range)) + 2 * (size_t)__builtin_amdgcn_readfirstlane(e);
-                        uint32_t i = rg[0];
-                        const uint32_t end = rg[1];
-                        while (i < end) {
-                            const HQ_CONST TrieNode* nd = ro(P.nodes) + i;
-                            const uint32_t need = nd->need, su = nd->skip_unit;
-                            const bool hit = (m & need) == need;
-                            if (!__any(hit)) {
-                                i = __builtin_amdgcn_readfirstlane(su >> 5);
-                                continue;
-                            }
-                            if (hit) {
-                                const int u = (int)(su & 31u);
-                                const uint32_t idx =
-                                    (u >= b) ? hqlayout::high_neighbour(ro(P.segoff), tiles, q, Tb, u - b, t)
-                                             : hqlayout::low_neighbour(L, u, offDlo, offUlo, s_rank);
-                                U += nd->rate * (double)x[idx];
-                            }
-                            i = __builtin_amdgcn_readfirstlane(i + 1);
-                        }
-                    }
-                }
-            }
-            U *= is_dn;
-            D *= is_up;
-            const double mu_m = mu_hi + mu_lo;
-            if (MODE == M_RESID) {
-                const double lm = (m == full) ? 0.0 : P.Lam;
-                const double self = (double)x[offSelf + t] * is_self;
-                const double in = pdn * U + pup * D;
-                const double out = pself * self * (lm + mu_m);
-                acc0 += fabs(in - out);
-                acc1 += out;
-            } else {
-                const double inv = 1.0 / (P.Lam + mu_m);
-                const double Ut = U * inv, Dt = D * inv;
-                if (MODE == M_PASS1) {
-                    acc0 += Ut;
-                    acc1 += mu_m * Dt;
-                } else {
-                    const double p = alpha * Ut + beta * Dt;
-                    const uint32_t o = offSelf + t;
-                    if (TRACK_DELTA) acc2 = fmax(acc2, fabs(p - (double)x[o] * is_self));
-                    const T stored = (T)(p * s_self);
-                    x[o] = stored;
-                    const double ps = (double)stored * is_self;
-                    acc0 += ps;
-                    acc1 += mu_m * ps;
-                }
-            }
-        }
-    }
+    for (uint32_t si = it.begin; si < it.end; si += it.step)
+        segment_update<T, MODE, TRACK_DELTA, STORED>(P, A, x, si, s_rank, s_unrank, s_qstart, ms, acc0, acc1, acc2);
     block_partial3(acc0, acc1, acc2, P.partials);
 }
 
@@ -413,60 +446,71 @@ __global__ __launch_bounds__(HQ_WG) void coef_kernel(SweepParams P, LayerArgs A,
 // Initial iterate of one layer: uniform 1/C(N,n) (Algorithm 1 step 2),
 // product form prod_{u in m} x_u / e_n(x), or a given state (bitmask order,
 // original unit labels mapped through `orig_bit`).  Partials for lambda(n), mu(n).
+// Initial values of one segment (wave-level): uniform 1/C(N,n)
+// (Algorithm 1 step 2), product form prod_{u in m} x_u / e_n(x), or a given
+// state (bitmask order, original labels through `orig_bit`).
+template <typename T>
+__device__ __forceinline__ void init_segment(const SweepParams& P, const LayerArgs& A, T* __restrict__ x,
+                                             uint32_t si, int init_mode, const double* __restrict__ xu,
+                                             const double* __restrict__ given,
+                                             const uint32_t* __restrict__ orig_bit, double& acc0, double& acc1) {
+    const int lane = threadIdx.x & 63;
+    const int n = A.n, b = P.b, H = P.H, N = P.N;
+    const uint32_t tiles = 1u << H;
+    const double sc_self = P.scale[n], is_self = P.inv_scale[n];
+    const uint32_t d = ro(P.seg_desc)[A.desc_base + si];
+    const int q = (int)(d & 15u);
+    const uint32_t Tb = d >> 4;
+    const uint32_t off = ro(P.segoff)[hqlayout::seg_index(q, Tb, tiles)];
+    const uint32_t Tabs = Tb << b;
+    double mu_hi = 0.0;
+    for (int k = 0; k < H; ++k)
+        if ((Tb >> k) & 1u) mu_hi += ro(P.nu)[b + k];
+    const uint32_t cnt = ro(P.binom)[b * 32 + q];
+    const uint32_t qs = P.lo_qstart[q];
+    for (uint32_t t = lane; t < cnt; t += 64) {
+        const uint32_t L = P.lo_unrank[qs + t];
+        const uint32_t m = Tabs | L;
+        double p;
+        if (n == 0 || n == N) {
+            p = 1.0;
+        } else if (init_mode == 1) {
+            double pr = 1.0;
+            for (int u = 0; u < N; ++u)
+                if ((m >> u) & 1u) pr *= xu[u];
+            p = pr / A.e_n;
+        } else if (init_mode == 2) {
+            uint32_t mo = 0;
+            for (int u = 0; u < N; ++u)
+                if ((m >> u) & 1u) mo |= orig_bit[u];
+            p = given[mo];
+        } else {
+            p = 1.0 / (double)A.count;
+        }
+        const T stored = (T)(p * sc_self);
+        x[off + t] = stored;
+        const double ps = (double)stored * is_self;
+        double mu_lo = 0.0;
+        for (int l = 0; l < b; ++l)
+            if ((L >> l) & 1u) mu_lo += ro(P.nu)[l];
+        acc0 += ps;
+        acc1 += (mu_hi + mu_lo) * ps;
+    }
+}
+
+// Initial iterate of one layer; partials for lambda(n), mu(n).  Same
+// wave-granular traversal (and so the same summation order of the layer
+// sums) as the layer kernels: a resumed iterate reproduces the
+// uninterrupted run bit for bit.
 template <typename T>
 __global__ __launch_bounds__(HQ_WG) void init_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
                                                      const double* __restrict__ xu,
                                                      const double* __restrict__ given,
                                                      const uint32_t* __restrict__ orig_bit) {
-    // same wave-granular traversal (and so the same summation order of the
-    // layer sums) as the layer kernels: a resumed iterate reproduces the
-    // uninterrupted run bit for bit
-    const int lane = threadIdx.x & 63;
-    const int n = A.n, b = P.b, H = P.H, N = P.N;
-    const uint32_t tiles = 1u << H;
-    const double sc_self = P.scale[n], is_self = P.inv_scale[n];
     double acc0 = 0.0, acc1 = 0.0;
     const WaveIter it = wave_iter(A.groups);
-    for (uint32_t si = it.begin; si < it.end; si += it.step) {
-        const uint32_t d = ro(P.seg_desc)[A.desc_base + si];
-        const int q = (int)(d & 15u);
-        const uint32_t Tb = d >> 4;
-        const uint32_t off = ro(P.segoff)[hqlayout::seg_index(q, Tb, tiles)];
-        const uint32_t Tabs = Tb << b;
-        double mu_hi = 0.0;
-        for (int k = 0; k < H; ++k)
-            if ((Tb >> k) & 1u) mu_hi += ro(P.nu)[b + k];
-        const uint32_t cnt = ro(P.binom)[b * 32 + q];
-        const uint32_t qs = P.lo_qstart[q];
-        for (uint32_t t = lane; t < cnt; t += 64) {
-            const uint32_t L = P.lo_unrank[qs + t];
-            const uint32_t m = Tabs | L;
-            double p;
-            if (n == 0 || n == N) {
-                p = 1.0;
-            } else if (A.init_mode == 1) {
-                double pr = 1.0;
-                for (int u = 0; u < N; ++u)
-                    if ((m >> u) & 1u) pr *= xu[u];
-                p = pr / A.e_n;
-            } else if (A.init_mode == 2) {
-                uint32_t mo = 0;
-                for (int u = 0; u < N; ++u)
-                    if ((m >> u) & 1u) mo |= orig_bit[u];
-                p = given[mo];
-            } else {
-                p = 1.0 / (double)A.count;
-            }
-            const T stored = (T)(p * sc_self);
-            x[off + t] = stored;
-            const double ps = (double)stored * is_self;
-            double mu_lo = 0.0;
-            for (int l = 0; l < b; ++l)
-                if ((L >> l) & 1u) mu_lo += ro(P.nu)[l];
-            acc0 += ps;
-            acc1 += (mu_hi + mu_lo) * ps;
-        }
-    }
+    for (uint32_t si = it.begin; si < it.end; si += it.step)
+        init_segment<T>(P, A, x, si, A.init_mode, xu, given, orig_bit, acc0, acc1);
     block_partial3(acc0, acc1, 0.0, P.partials);
 }
 
@@ -599,6 +643,208 @@ __global__ void widen_kernel(const float* __restrict__ src, double* __restrict__
     if (i < count) dst[begin + i] = (double)src[begin + i] * factor;
 }
 
+// ---------------------------------------------------------------------------
+// Batched solve: a persistent grid; each work-group takes the next instance
+// from a work queue (largest first, as the host orders them) and runs all
+// of Algorithm 1 on it — initial iterate, Gauss-Seidel layer sweeps, inner
+// form, residual checks with the same adaptive schedule as the single
+// solver — with work-group barriers between layers and no other
+// synchronisation.  Waves of the group share each layer's segments.
+// ---------------------------------------------------------------------------
+template <int BS>
+__device__ __forceinline__ void block_sum3(double& a0, double& a1, double& a2, double (*s_red)[BS / 64]) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_max(a2);
+    __syncthreads();
+    if (lane == 0) {
+        s_red[0][w] = a0;
+        s_red[1][w] = a1;
+        s_red[2][w] = a2;
+    }
+    __syncthreads();
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    for (int i = 0; i < BS / 64; ++i) {
+        b0 += s_red[0][i];
+        b1 += s_red[1][i];
+        b2 = fmax(b2, s_red[2][i]);
+    }
+    a0 = b0;
+    a1 = b1;
+    a2 = b2;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void batch_layer(const SweepParams& P, const LayerArgs& A, T* x, const uint16_t* s_rank,
+                                            const uint16_t* s_unrank, const uint32_t* s_qstart,
+                                            const ModeScalars& ms, double& a0, double& a1, double& a2) {
+    const uint32_t NW = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (A.stored) {
+        for (uint32_t si = wv; si < A.groups; si += NW)
+            segment_update<T, MODE, false, true>(P, A, x, si, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
+    } else {
+        for (uint32_t si = wv; si < A.groups; si += NW)
+            segment_update<T, MODE, false, false>(P, A, x, si, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
+    }
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__ items, BatchOut* __restrict__ outs,
+                                                   int count, unsigned int* __restrict__ next) {
+    __shared__ uint16_t s_rank[1 << HQ_MAXB];
+    __shared__ uint16_t s_unrank[1 << HQ_MAXB];
+    __shared__ uint32_t s_qstart[HQ_MAXB + 2];
+    __shared__ double s_lam[32], s_mu[32], s_alpha[32], s_pn[32];
+    __shared__ double s_red[3][BS / 64];
+    __shared__ int s_item, s_go, s_next;
+    const int tid = threadIdx.x;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (int)__hip_atomic_fetch_add(next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int ii = __builtin_amdgcn_readfirstlane(s_item);
+        if (ii >= count) break;
+        const BatchItem& B = items[ii];
+        const SweepParams& P = B.P;
+        T* x = (T*)B.x;
+        const int N = P.N, b = P.b;
+        for (int i = tid; i < (1 << b); i += BS) {
+            s_rank[i] = P.lo_rank[i];
+            s_unrank[i] = P.lo_unrank[i];
+        }
+        if (tid <= b + 1) s_qstart[tid] = P.lo_qstart[tid];
+        __syncthreads();
+        // initial iterate and its layer scalars (13)-(14)
+        for (int n = 0; n <= N; ++n) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            const uint32_t NW = BS / 64, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            for (uint32_t si = wv; si < B.layers[n].groups; si += NW)
+                init_segment<T>(P, B.layers[n], x, si, B.init_mode, B.xu, B.given, B.orig_bit, a0, a1);
+            block_sum3<BS>(a0, a1, a2, s_red);
+            if (tid == 0) {
+                s_lam[n] = (n == N) ? 0.0 : P.Lam * a0;
+                s_mu[n] = a1;
+                s_alpha[n] = 0.0;
+            }
+        }
+        __syncthreads();
+        int k = 0, checks = 0, status = HQ_ERR_NOT_CONVERGED_CODE, next_check = B.check_every > 0 ? B.check_every : 8;
+        double res = -1.0, prev_res = -1.0;
+        int prev_k = 0, stall = 0;
+        if (next_check > B.max_iters) next_check = B.max_iters;
+        while (k < B.max_iters) {
+            for (int n = 1; n <= N - 1; ++n) {
+                const LayerArgs& A = B.layers[n];
+                if (!B.inner_one) {
+                    const ModeScalars ms = mode_scalars<M_PASS1>(P, n, 0, s_lam, s_mu, s_alpha, s_pn);
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+                    batch_layer<T, M_PASS1>(P, A, x, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
+                    block_sum3<BS>(a0, a1, a2, s_red);
+                    if (tid == 0) s_alpha[n] = ms.beta * a1 / (P.Lam * a0);
+                    __syncthreads();
+                }
+                const ModeScalars ms = mode_scalars<M_WRITE>(P, n, B.inner_one, s_lam, s_mu, s_alpha, s_pn);
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+                batch_layer<T, M_WRITE>(P, A, x, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
+                block_sum3<BS>(a0, a1, a2, s_red);
+                if (tid == 0) {
+                    s_alpha[n] = ms.alpha;
+                    s_lam[n] = P.Lam * a0;
+                    s_mu[n] = a1;
+                }
+                __syncthreads();
+            }
+            ++k;
+            if (k < next_check && k < B.max_iters) continue;
+            // residual of (1): p(n) of (10), then every layer
+            if (tid == 0) {
+                double g = 1.0, G = 1.0;
+                for (int n = 1; n <= N; ++n) {
+                    g = g * s_lam[n - 1] / s_mu[n];
+                    G += g;
+                }
+                g = 1.0;
+                for (int n = 0; n <= N; ++n) {
+                    if (n > 0) g = g * s_lam[n - 1] / s_mu[n];
+                    s_pn[n] = g / G;
+                }
+            }
+            __syncthreads();
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int n = 0; n <= N; ++n) {
+                const ModeScalars ms = mode_scalars<M_RESID>(P, n, 0, s_lam, s_mu, s_alpha, s_pn);
+                batch_layer<T, M_RESID>(P, B.layers[n], x, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
+            }
+            block_sum3<BS>(a0, a1, a2, s_red);
+            ++checks;
+            if (tid == 0) {
+                res = a1 > 0.0 ? a0 / a1 : 0.0;
+                int go = 1;
+                if (!isfinite(res)) {
+                    status = HQ_ERR_NUMERIC_CODE;
+                    go = 0;
+                } else if (res <= B.tol) {
+                    status = 0;
+                    go = 0;
+                } else {
+                    if (sizeof(T) == 4 && prev_res > 0.0 && res > 0.8 * prev_res && ++stall >= 3) go = 0;
+                    if (B.check_every > 0) {
+                        next_check = k + B.check_every;
+                    } else if (prev_res > 0.0 && res < prev_res) {
+                        const double rate = pow(res / prev_res, 1.0 / (double)max(1, k - prev_k));
+                        int step = (int)ceil(log(B.tol / res) / log(rate));
+                        next_check = k + max(1, min(step, 64));
+                    } else {
+                        next_check = k + 8;
+                    }
+                    if (next_check > B.max_iters) next_check = B.max_iters;
+                }
+                prev_res = res;
+                prev_k = k;
+                s_go = go;
+                s_next = next_check;
+            }
+            __syncthreads();
+            next_check = s_next;  // every thread takes thread 0's schedule
+            if (!s_go) break;
+        }
+        // publish the instance's scalars where the single-instance entry points read them
+        if (tid == 0) {
+            double g = 1.0, G = 1.0;
+            for (int n = 1; n <= N; ++n) {
+                g = g * s_lam[n - 1] / s_mu[n];
+                G += g;
+            }
+            g = 1.0;
+            double mass = 0.0;
+            for (int n = 0; n <= N; ++n) {
+                if (n > 0) g = g * s_lam[n - 1] / s_mu[n];
+                const double pn = g / G;
+                P.sc.pn[n] = pn;
+                P.sc.lam[n] = s_lam[n];
+                P.sc.mu[n] = s_mu[n];
+                P.sc.alpha[n] = s_alpha[n];
+                mass += pn * ((n == N) ? 1.0 : s_lam[n] / P.Lam);
+            }
+            P.sc.misc[0] = res;
+            P.sc.misc[1] = mass;
+            P.sc.misc[2] = (status == HQ_ERR_NUMERIC_CODE) ? 1.0 : 0.0;
+            BatchOut o;
+            o.iterations = k;
+            o.checks = checks;
+            o.status = status;
+            o.pad = 0;
+            o.residual = res;
+            outs[ii] = o;
+        }
+    }
+}
+
+__global__ void reset_counter_kernel(unsigned int* c) {
+    if (threadIdx.x == 0) *c = 0u;
+}
+
 }  // namespace hq
 
 // ---------------------------------------------------------------------------
@@ -688,6 +934,27 @@ hipError_t launch_marginal(bool fp32, const SweepParams& P, const LayerArgs& A, 
         hipLaunchKernelGGL((marginal_kernel<double>), grid, block, 0, s, P, A, (const double*)x, part);
     hipLaunchKernelGGL(marginal_finalize_kernel, dim3(1), dim3(32), 0, s, P, (const double*)part,
                        grid_for(A.groups), rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(bool fp32, int block, const BatchItem* items, BatchOut* outs, int count,
+                        unsigned int* next, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, next);
+#define HQ_BATCH_CASE(BSZ)                                                                                    \
+    case BSZ:                                                                                               \
+        if (fp32)                                                                                           \
+            hipLaunchKernelGGL((batch_kernel<float, BSZ>), dim3(grid), dim3(BSZ), 0, s, items, outs, count, next); \
+        else                                                                                                \
+            hipLaunchKernelGGL((batch_kernel<double, BSZ>), dim3(grid), dim3(BSZ), 0, s, items, outs, count, next); \
+        break;
+    switch (block) {
+        HQ_BATCH_CASE(256)
+        HQ_BATCH_CASE(512)
+        HQ_BATCH_CASE(1024)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef HQ_BATCH_CASE
     return hipGetLastError();
 }
 
