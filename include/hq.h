@@ -33,6 +33,12 @@ extern "C" {
 #define HQ_MAX_N 30 /* 2^30 states; colex ranks and layer offsets fit in uint32 */
 
 typedef struct hq_ctx hq_ctx; /* opaque; owns its host and device memory */
+typedef struct hq_mlp hq_mlp; /* opaque; the warm-start network (see below) */
+
+#define HQ_MLP_IN 32      /* feature slots per unit (16 used, the rest zero) */
+#define HQ_MLP_HIDDEN 256 /* width of both hidden layers */
+#define HQ_MLP_PARAMS (HQ_MLP_IN * HQ_MLP_HIDDEN + HQ_MLP_HIDDEN + HQ_MLP_HIDDEN * HQ_MLP_HIDDEN + \
+                       HQ_MLP_HIDDEN + HQ_MLP_HIDDEN + 1)
 
 typedef enum {
     HQ_OK = 0,
@@ -62,7 +68,7 @@ enum {
     HQ_INIT_UNIFORM = 0, /* p_n(m) = 1 / C(N, n), as Algorithm 1 step 2 */
     HQ_INIT_PRODUCT = 1, /* p_n(m) proportional to prod_{u in m} x_u, x_u = rho_u / (1 - rho_u), from init_rho */
     HQ_INIT_STATE = 2,   /* resume: conditional probabilities p_n(m) from init_state (bitmask order) */
-    HQ_INIT_LEARNED = 3  /* product form with rho predicted by the loaded MLP (hq_mlp_load) */
+    HQ_INIT_LEARNED = 3  /* product form with rho predicted by opts.mlp (falls back to uniform) */
 };
 
 /* stopping rule */
@@ -86,6 +92,7 @@ typedef struct {
     const double* init_rho;   /* [N] per-unit utilisations for HQ_INIT_PRODUCT (copied) */
     const double* init_state; /* [2^N] conditional probabilities for HQ_INIT_STATE (copied) */
     void* stream;             /* hipStream_t to run on (e.g. torch's current stream); NULL = own stream */
+    const hq_mlp* mlp;        /* network for HQ_INIT_LEARNED (evaluated during hq_create) */
 } hq_options;
 
 typedef struct {
@@ -99,6 +106,8 @@ typedef struct {
     double state_updates_per_s;  /* (2^N - 2) * iterations / sweep_seconds */
     double mass_error;           /* sum(P) - 1 before the final renormalisation */
     double max_layer_drift;      /* max_n |sum_{C_n} p_n - 1| at the end */
+    int warm_used;               /* 1 if a product-form / learned initial iterate was kept, 0 if
+                                    the uniform start was used (no warm start, or fallback) */
 } hq_info;
 
 /* Fill *opts with the defaults (FP64, closed inner form, uniform init,
@@ -186,8 +195,51 @@ hq_status hq_layer_scalars(const hq_ctx* ctx, double* out);
  * context's device, on `stream` (NULL = the context's stream). */
 hq_status hq_state_device(const hq_ctx* ctx, double* dev_P, void* stream);
 
-/* Number of units, and the count of states 2^N, of a context. */
+/* Number of units of a context. */
 int hq_num_units(const hq_ctx* ctx);
+
+/* ---------------------------------------------------------------------
+ * Learned warm start: an MLP (HQ_MLP_IN -> 256 -> 256 -> 1, ReLU, sigmoid
+ * output) that predicts each unit's busy probability from scale-free
+ * features of the instance.  Its prediction seeds the product-form initial
+ * iterate p_n(m) proportional to prod_{u in m} rho/(1-rho), normalised per
+ * layer with elementary symmetric polynomials (a uniform rho gives the
+ * 1/C(N,n) start of Algorithm 1).  Products run on the matrix cores with
+ * BF16 operands and FP32 accumulation; master weights and Adam state are
+ * FP32.  Parameters are packed as W1[IN*256] (row = feature), b1[256],
+ * W2[256*256] (row = input), b2[256], w3[256], b3[1].
+ * ------------------------------------------------------------------- */
+
+/* Per-unit features [N * HQ_MLP_IN] of an instance (host computation; same
+ * arguments as hq_create): relative service rate, shares of demand that
+ * rank the unit at positions 0..7 and 8+, offered load, load-discounted
+ * exposure, N/32, rate relative to the fastest unit, first-choice share
+ * times N, and a constant 1. */
+hq_status hq_mlp_features(int N, int J, const double* lambda_j, const double* mu_i,
+                          const int32_t* pref_lists, float* features);
+
+/* New network on `device` (< 0: current) with Glorot-uniform weights from `seed`. */
+hq_status hq_mlp_create(int device, unsigned long long seed, hq_mlp** out);
+void hq_mlp_destroy(hq_mlp* mlp); /* NULL-safe */
+
+/* Copy the FP32 parameters out of / into the network ([HQ_MLP_PARAMS]). */
+hq_status hq_mlp_get_params(const hq_mlp* mlp, float* params);
+hq_status hq_mlp_set_params(hq_mlp* mlp, const float* params);
+
+/* Predictions y[rows] for features X[rows * HQ_MLP_IN]. */
+hq_status hq_mlp_forward(hq_mlp* mlp, const float* X, int rows, float* y);
+
+/* One forward + backward pass of the mean squared error of rows (X, t):
+ * gradient of the loss w.r.t. the packed parameters into grad
+ * [HQ_MLP_PARAMS], the loss into *loss (nullable). */
+hq_status hq_mlp_gradient(hq_mlp* mlp, const float* X, const float* t, int rows, float* grad,
+                          float* loss);
+
+/* Adam training (lr, beta 0.9/0.999) of the mean squared error over
+ * `epochs` shuffled passes (seeded) with minibatches of `batch` rows
+ * (a multiple of 32); epoch_loss [epochs] (nullable) gets the mean loss. */
+hq_status hq_mlp_train(hq_mlp* mlp, const float* X, const float* t, int rows, int epochs, int batch,
+                       float lr, unsigned long long seed, float* epoch_loss);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["hq_kernels.hip", "hq_api.cpp"]
+SOURCES = ["hq_kernels.hip", "hq_api.cpp", "hq_mlp.hip", "hq_mlp_api.cpp"]
 OUT = os.path.join(HERE, "libhq.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -46,6 +46,14 @@ hq_status fail(hq_status s, const std::string& msg) {
     return s;
 }
 
+}  // namespace
+
+void hq_set_error(const std::string& msg) { g_err = msg; }
+hq_status hq_mlp_predict_instance(const hq_mlp* mc, int N, int J, const double* lam, const double* mu,
+                                  const int32_t* pref, std::vector<double>& rho);
+
+namespace {
+
 struct HipError {
     hipError_t e;
     const char* what;
@@ -109,6 +117,7 @@ struct hq_ctx {
     unsigned int* d_counters = nullptr;
     SweepParams P64{}, P32{};
     bool have_iterate = false;
+    bool learned = false;      // product-form weights came from the network
     bool active_fp32 = false;  // storage of the current iterate
     int iterations_done = 0;
 
@@ -323,7 +332,7 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         return fail(HQ_ERR_INVALID_ARG, "unknown precision");
     if (o.inner != HQ_INNER_CLOSED && o.inner != HQ_INNER_ONE) return fail(HQ_ERR_INVALID_ARG, "unknown inner mode");
     if (o.init < HQ_INIT_UNIFORM || o.init > HQ_INIT_LEARNED) return fail(HQ_ERR_INVALID_ARG, "unknown init mode");
-    if (o.init == HQ_INIT_LEARNED) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_LEARNED needs the MLP entry points");
+    if (o.init == HQ_INIT_LEARNED && !o.mlp) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_LEARNED needs opts.mlp");
     if (o.stop != HQ_STOP_RESIDUAL && o.stop != HQ_STOP_DELTA) return fail(HQ_ERR_INVALID_ARG, "unknown stop rule");
     if (o.init == HQ_INIT_PRODUCT && !o.init_rho) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_PRODUCT needs init_rho");
     if (o.init == HQ_INIT_STATE && !o.init_state) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_STATE needs init_state");
@@ -361,6 +370,17 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->rho_init.resize(N);
         for (int u = 0; u < N; ++u) c->rho_init[u] = o.init_rho[c->orig[u]];
     }
+    if (o.init == HQ_INIT_LEARNED) {
+        // predicted utilisations seed the product form; the network runs on its own device
+        std::vector<double> rho;
+        hq_status ps = hq_mlp_predict_instance(o.mlp, N, J, lam, mu, pref, rho);
+        if (ps != HQ_OK) return ps;
+        c->rho_init.resize(N);
+        for (int u = 0; u < N; ++u) c->rho_init[u] = rho[c->orig[u]];
+        c->opts.init = HQ_INIT_PRODUCT;
+        c->learned = true;
+    }
+    c->opts.mlp = nullptr;
     if (o.init == HQ_INIT_STATE) c->state_init.assign(o.init_state, o.init_state + (1ull << N));
     c->opts.init_rho = nullptr;
     c->opts.init_state = nullptr;
@@ -613,6 +633,23 @@ hq_status solve_impl(hq_ctx* c, double tol, hq_info* info) {
     double sweep_ms = 0.0;
     try {
         run_init(c, prec != HQ_FP64);
+        inf.warm_used = 0;
+        if (c->opts.init == HQ_INIT_PRODUCT) {
+            // cold start as fallback: keep the warm iterate only if its balance
+            // residual is below the uniform start's
+            double mw[3], mc[3];
+            run_residual(c, mw);
+            const int saved = c->opts.init;
+            c->opts.init = HQ_INIT_UNIFORM;
+            run_init(c, prec != HQ_FP64);
+            run_residual(c, mc);
+            c->opts.init = saved;
+            inf.checks += 2;
+            if (std::isfinite(mw[0]) && mw[0] < mc[0]) {
+                run_init(c, prec != HQ_FP64);
+                inf.warm_used = 1;
+            }
+        }
         int k = 0, next = fixed > 0 ? fixed : std::min(8, max_iters);
         double last_res = -1.0, prev_res = -1.0;
         int prev_k = 0, stall = 0, fp64_from = prec == HQ_FP64 ? 0 : -1;

@@ -30,7 +30,11 @@ STATUS_NAMES = {0: "HQ_OK", 1: "HQ_ERR_INVALID_ARG", 2: "HQ_ERR_OUT_OF_MEMORY", 
 # every symbol include/hq.h declares
 EXPORTED = ["hq_default_options", "hq_create", "hq_solve", "hq_marginals", "hq_state", "hq_solve_batch",
             "hq_destroy", "hq_last_error", "hq_iterate", "hq_reset", "hq_residual", "hq_conditional",
-            "hq_layer_scalars", "hq_state_device", "hq_num_units"]
+            "hq_layer_scalars", "hq_state_device", "hq_num_units", "hq_mlp_features", "hq_mlp_create",
+            "hq_mlp_destroy", "hq_mlp_get_params", "hq_mlp_set_params", "hq_mlp_forward", "hq_mlp_gradient",
+            "hq_mlp_train"]
+HQ_MLP_IN, HQ_MLP_HIDDEN = 32, 256
+HQ_MLP_PARAMS = HQ_MLP_IN * HQ_MLP_HIDDEN + HQ_MLP_HIDDEN + HQ_MLP_HIDDEN * HQ_MLP_HIDDEN + 2 * HQ_MLP_HIDDEN + 1
 
 
 class HQError(RuntimeError):
@@ -44,7 +48,8 @@ class hq_options(ctypes.Structure):
                 ("stop", ctypes.c_int), ("max_iters", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("tile_bits", ctypes.c_int), ("device", ctypes.c_int), ("stored_layers", ctypes.c_int),
                 ("init_rho", ctypes.POINTER(ctypes.c_double)),
-                ("init_state", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p)]
+                ("init_state", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
+                ("mlp", ctypes.c_void_p)]
 
 
 class hq_info(ctypes.Structure):
@@ -52,7 +57,7 @@ class hq_info(ctypes.Structure):
                 ("fp64_iterations", ctypes.c_int), ("residual", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("sweep_seconds", ctypes.c_double),
                 ("state_updates_per_s", ctypes.c_double), ("mass_error", ctypes.c_double),
-                ("max_layer_drift", ctypes.c_double)]
+                ("max_layer_drift", ctypes.c_double), ("warm_used", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -102,6 +107,23 @@ def load(path: str = LIB_PATH):
     L.hq_state_device.restype = c_int
     L.hq_num_units.argtypes = [vp]
     L.hq_num_units.restype = c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.hq_mlp_features.argtypes = [c_int, c_int, dp, dp, ctypes.POINTER(ctypes.c_int32), fp]
+    L.hq_mlp_features.restype = c_int
+    L.hq_mlp_create.argtypes = [c_int, ctypes.c_ulonglong, ctypes.POINTER(vp)]
+    L.hq_mlp_create.restype = c_int
+    L.hq_mlp_destroy.argtypes = [vp]
+    L.hq_mlp_destroy.restype = None
+    L.hq_mlp_get_params.argtypes = [vp, fp]
+    L.hq_mlp_get_params.restype = c_int
+    L.hq_mlp_set_params.argtypes = [vp, fp]
+    L.hq_mlp_set_params.restype = c_int
+    L.hq_mlp_forward.argtypes = [vp, fp, c_int, fp]
+    L.hq_mlp_forward.restype = c_int
+    L.hq_mlp_gradient.argtypes = [vp, fp, fp, c_int, fp, fp]
+    L.hq_mlp_gradient.restype = c_int
+    L.hq_mlp_train.argtypes = [vp, fp, fp, c_int, c_int, c_int, ctypes.c_float, ctypes.c_ulonglong, fp]
+    L.hq_mlp_train.restype = c_int
     _lib = L
     return L
 
@@ -143,7 +165,7 @@ class Context:
 
 
 def hq_create(N: int, J: int, lambda_j, mu_i, pref_lists, opts: Optional[hq_options] = None,
-              *, init_rho=None, init_state=None, stream=None, **fields) -> Context:
+              *, init_rho=None, init_state=None, stream=None, mlp=None, **fields) -> Context:
     """hq_create(N, J, lambda_j[J], mu_i[N], pref_lists[J*N], opts).  Keyword
     fields (precision=..., inner=..., ...) override entries of opts."""
     L = load()
@@ -170,6 +192,10 @@ def hq_create(N: int, J: int, lambda_j, mu_i, pref_lists, opts: Optional[hq_opti
             o.init = HQ_INIT_STATE
     if stream is not None:
         o.stream = ctypes.c_void_p(int(stream))
+    if mlp is not None:
+        o.mlp = mlp.handle
+        if "init" not in fields:
+            o.init = HQ_INIT_LEARNED
     h = ctypes.c_void_p()
     _check(L.hq_create(int(N), int(J), _dptr(lam), _dptr(mu), pref.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                        ctypes.byref(o), ctypes.byref(h)))
@@ -253,3 +279,81 @@ def hq_num_units(ctx: Context) -> int:
 def create_from_instance(inst, **kw) -> Context:
     """hq_create from a seeded instance (paper_2603_03019_amd.instances)."""
     return hq_create(inst.N, inst.J, inst.lam, inst.nu, inst.pref, **kw)
+
+
+# ---------------------------------------------------------------- warm-start network
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class MLP:
+    """Owns an hq_mlp* (the warm-start network)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        try:
+            hq_mlp_destroy(self)
+        except Exception:
+            pass
+
+
+def hq_mlp_create(device: int = -1, seed: int = 0) -> MLP:
+    h = ctypes.c_void_p()
+    _check(load().hq_mlp_create(int(device), int(seed), ctypes.byref(h)))
+    return MLP(h)
+
+
+def hq_mlp_destroy(m: MLP):
+    if m is not None and m.handle:
+        load().hq_mlp_destroy(m.handle)
+        m.handle = None
+
+
+def hq_mlp_features(N, J, lambda_j, mu_i, pref_lists) -> np.ndarray:
+    lam = np.ascontiguousarray(lambda_j, dtype=np.float64).reshape(-1)
+    mu = np.ascontiguousarray(mu_i, dtype=np.float64).reshape(-1)
+    pref = np.ascontiguousarray(pref_lists, dtype=np.int32).reshape(-1)
+    out = np.zeros((N, HQ_MLP_IN), dtype=np.float32)
+    _check(load().hq_mlp_features(int(N), int(J), _dptr(lam), _dptr(mu),
+                                  pref.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _fptr(out)))
+    return out
+
+
+def hq_mlp_get_params(m: MLP) -> np.ndarray:
+    p = np.zeros(HQ_MLP_PARAMS, dtype=np.float32)
+    _check(load().hq_mlp_get_params(m.handle, _fptr(p)))
+    return p
+
+
+def hq_mlp_set_params(m: MLP, params) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == HQ_MLP_PARAMS
+    _check(load().hq_mlp_set_params(m.handle, _fptr(p)))
+
+
+def hq_mlp_forward(m: MLP, X) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, HQ_MLP_IN)
+    y = np.zeros(X.shape[0], dtype=np.float32)
+    _check(load().hq_mlp_forward(m.handle, _fptr(X), X.shape[0], _fptr(y)))
+    return y
+
+
+def hq_mlp_gradient(m: MLP, X, t):
+    X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, HQ_MLP_IN)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    g = np.zeros(HQ_MLP_PARAMS, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(load().hq_mlp_gradient(m.handle, _fptr(X), _fptr(t), X.shape[0], _fptr(g), ctypes.byref(loss)))
+    return g, float(loss.value)
+
+
+def hq_mlp_train(m: MLP, X, t, *, epochs: int, batch: int = 1024, lr: float = 1e-3, seed: int = 0):
+    X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, HQ_MLP_IN)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    losses = np.zeros(max(epochs, 1), dtype=np.float32)
+    _check(load().hq_mlp_train(m.handle, _fptr(X), _fptr(t), X.shape[0], int(epochs), int(batch), float(lr),
+                               int(seed), _fptr(losses)))
+    return losses[:epochs]
