@@ -63,6 +63,8 @@ def lib():
         L.orc_marginals.restype = None
         L.orc_marginals.argtypes = [ctypes.c_int, d, d, d]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_balance_terms.restype = None
+        L.orc_balance_terms.argtypes = [ctypes.c_int, ctypes.c_int, d, d, i32, ctypes.c_longlong, u32, d, d, d]
         _lib = L
     return _lib
 
@@ -206,3 +208,14 @@ def closed_form_alpha(Lprev: float, beta: float, sums: np.ndarray) -> float:
     A = sums[1] / Lprev
     B = beta * sums[3]
     return (B / (1.0 - A)) / Lprev
+
+
+def balance_terms(inst, states: np.ndarray, P: np.ndarray):
+    """(inflow - outflow, outflow) of (1) at the sampled states."""
+    lam, nu, pref = _args(inst)
+    st = np.ascontiguousarray(states, dtype=np.uint32)
+    out = np.zeros(len(st))
+    of = np.zeros(len(st))
+    lib().orc_balance_terms(inst.N, inst.J, _dp(lam), _dp(nu), _ip(pref), len(st), _up(st),
+                            _dp(np.ascontiguousarray(P, dtype=np.float64)), _dp(out), _dp(of))
+    return out, of

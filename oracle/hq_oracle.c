@@ -516,3 +516,33 @@ void orc_marginals(int N, const double* P, double* rho, double* pn) {
             if ((m >> u) & 1u) rho[u] += P[m];
     }
 }
+
+/* Balance terms of (1) for sampled states: out[i] = inflow - outflow at
+ * states[i], and outflow[i] = P(m)(lambda_m + mu_m), with P in bitmask order
+ * and Algorithm-3 coefficients generated per state. */
+void orc_balance_terms(int N, int J, const double* lam, const double* nu, const int32_t* pref,
+                       long long count, const uint32_t* states, const double* P, double* out,
+                       double* outflow) {
+    const uint32_t full = (N >= 32) ? 0xffffffffu : ((1u << N) - 1u);
+    double Lam = 0.0;
+    for (int j = 0; j < J; ++j) Lam += lam[j];
+#pragma omp parallel
+    {
+        double* a = (double*)malloc(sizeof(double) * N);
+#pragma omp for schedule(dynamic, 64)
+        for (long long i = 0; i < count; ++i) {
+            uint32_t m = states[i];
+            orc_up_coefficients(N, J, lam, pref, m, a);
+            double in = 0.0;
+            for (int u = 0; u < N; ++u) {
+                uint32_t bit = 1u << u;
+                if (m & bit) in += a[u] * P[m ^ bit];
+                else in += nu[u] * P[m | bit];
+            }
+            double o = P[m] * (((m == full) ? 0.0 : Lam) + state_mu(N, nu, m));
+            out[i] = in - o;
+            outflow[i] = o;
+        }
+        free(a);
+    }
+}

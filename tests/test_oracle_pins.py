@@ -399,3 +399,15 @@ def test_pins_catch_planted_mistakes(name, tmp_path):
                 None, dp(P), dp(pc), dp(lay), dp(st), None, None)
     err = np.abs(P - exact.dense_solve(inst)).sum()
     assert not (err <= 1e-6), f"mutant {name} escaped the dense pin (L1 {err:.2e})"
+
+
+def test_balance_terms_match_generator():
+    """Per-state balance terms (inflow - outflow) equal (P Q)_m with Q built
+    per source state, for an arbitrary (not stationary) P."""
+    inst = config_instance(3, 9, N=9, J=60)
+    P = np.random.default_rng(4).random(1 << 9)
+    Q = exact.generator_matrix(inst)
+    states = np.arange(1 << 9, dtype=np.uint32)
+    terms, out = cpu.balance_terms(inst, states, P)
+    np.testing.assert_allclose(terms, P @ Q, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(out, -np.diag(Q) * P, rtol=1e-13)
