@@ -1,0 +1,105 @@
+"""Learned warm start: training data from the solver itself, GPU training of
+the network, and the cold / heuristic / learned comparison.
+
+All arithmetic runs in libhq.so (batched solves, feature extraction, the
+network's forward/backward/Adam kernels); this module only orchestrates.
+
+* ``training_set``: solve a seeded pool of deployments (N ~ U{16..20},
+  J = 500, load ~ U[0.5, 0.9)) with one batched launch per chunk and return
+  the per-unit features with the solved busy probabilities as targets.
+* ``train``: fit a fresh network on that set (Adam, minibatches, on the GPU).
+* ``heuristic_rho``: the baseline product-form seed, each unit as an M/M/1/1
+  queue fed by the demand that ranks it first: a / (1 + a), a = load / nu.
+* ``evaluate``: iterations and time to the tolerance for the cold start
+  (1/C(N,n), Algorithm 1 step 2), the heuristic seed and the learned seed.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import hq
+from .instances import config_instance
+
+
+def training_set(count: int, *, first_index: int = 1000, tol: float = 1e-7, chunk: int = 512,
+                 verbose: bool = False):
+    """Features X [rows, HQ_MLP_IN] and targets t [rows] (busy probabilities)."""
+    X: List[np.ndarray] = []
+    t: List[np.ndarray] = []
+    for c0 in range(0, count, chunk):
+        insts = [config_instance(5, first_index + i) for i in range(c0, min(count, c0 + chunk))]
+        ctxs = [hq.create_from_instance(i, inner=hq.HQ_INNER_ONE) for i in insts]
+        t0 = time.perf_counter()
+        hq.hq_solve_batch(ctxs, tol)
+        for inst, ctx in zip(insts, ctxs):
+            rho, _ = hq.hq_marginals(ctx)
+            X.append(hq.hq_mlp_features(inst.N, inst.J, inst.lam, inst.nu, inst.pref))
+            t.append(rho.astype(np.float32))
+            hq.hq_destroy(ctx)
+        if verbose:
+            print(f"warmstart: solved {min(count, c0 + chunk)}/{count} training deployments "
+                  f"({time.perf_counter() - t0:.1f}s)", flush=True)
+    return np.concatenate(X), np.concatenate(t)
+
+
+def train(X: np.ndarray, t: np.ndarray, *, epochs: int = 40, batch: int = 1024, lr: float = 1e-3,
+          seed: int = 0, device: int = -1):
+    """A fresh network fitted on (X, t); returns (network, per-epoch loss)."""
+    m = hq.hq_mlp_create(device=device, seed=seed)
+    losses = hq.hq_mlp_train(m, X, t, epochs=epochs, batch=batch, lr=lr, seed=seed + 1)
+    return m, losses
+
+
+def heuristic_rho(inst) -> np.ndarray:
+    share0 = np.zeros(inst.N)
+    np.add.at(share0, inst.pref[:, 0], inst.lam)
+    a = share0 / inst.nu
+    return a / (1.0 + a)
+
+
+def evaluate(net, indices, *, tol: float = 1e-8, config: int = 6, verbose: bool = False,
+             overrides: Optional[dict] = None) -> Dict[str, list]:
+    """Per instance: iterations, seconds and final residual for the three starts."""
+    out: Dict[str, list] = {"cold": [], "heuristic": [], "learned": [], "warm_kept": [], "N": []}
+    for idx in indices:
+        inst = config_instance(config, idx, **(overrides or {}))
+        runs = {
+            "cold": dict(),
+            "heuristic": dict(init_rho=heuristic_rho(inst)),
+            "learned": dict(mlp=net),
+        }
+        # the learned start also pays for its features and inference (done in hq_create)
+        t0 = time.perf_counter()
+        feats = hq.hq_mlp_features(inst.N, inst.J, inst.lam, inst.nu, inst.pref)
+        hq.hq_mlp_forward(net, feats)
+        infer_s = time.perf_counter() - t0
+        for name, kw in runs.items():
+            ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE, **kw)
+            info = hq.hq_solve(ctx, tol)
+            sec = info["seconds"] + (infer_s if name == "learned" else 0.0)
+            out[name].append((info["iterations"], sec, info["residual"]))
+            if name == "learned":
+                out["warm_kept"].append(info["warm_used"])
+            hq.hq_destroy(ctx)
+        out["N"].append(inst.N)
+        if verbose:
+            print(f"warmstart: eval {idx}: cold {out['cold'][-1][0]} it, heuristic "
+                  f"{out['heuristic'][-1][0]} it, learned {out['learned'][-1][0]} it", flush=True)
+    return out
+
+
+def summarize(res: Dict[str, list]) -> dict:
+    s = {}
+    for name in ("cold", "heuristic", "learned"):
+        it = np.array([r[0] for r in res[name]], float)
+        sec = np.array([r[1] for r in res[name]], float)
+        s[name] = {"iterations_mean": float(it.mean()), "seconds_mean": float(sec.mean()),
+                   "max_residual": float(max(r[2] for r in res[name]))}
+    s["learned_vs_cold_time"] = s["cold"]["seconds_mean"] / s["learned"]["seconds_mean"]
+    s["learned_vs_cold_iterations"] = s["cold"]["iterations_mean"] / s["learned"]["iterations_mean"]
+    s["warm_kept_fraction"] = float(np.mean(res["warm_kept"]))
+    s["instances"] = len(res["N"])
+    return s
