@@ -1,0 +1,99 @@
+"""Parity at the full benchmark size: N = 26 units, J = 1000 clustered
+demand nodes, load 0.7, in the launch configuration bench.py times.
+
+The oracle cannot run Algorithm 1 to convergence at 2^26 states inside a
+test, so it checks outputs it can compute one by one:
+* one layer update of (12): from exported snapshots after iterations 2
+  and 3, the oracle recomputes sampled states of several layers (its own
+  Algorithm-3 coefficients), with alpha_n and beta_n rebuilt on the host
+  from plain sums of the snapshots (13)-(14);
+* at convergence, sampled balance terms of (1) and the per-unit marginals
+  of the exported distribution.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpu
+from paper_2603_03019_amd import hq
+from paper_2603_03019_amd.instances import config_instance
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def big():
+    inst = config_instance(3, 0)  # the benchmark workload
+    assert inst.N == 26 and inst.J == 1000
+    m = np.arange(1 << inst.N, dtype=np.uint32)
+    pop = np.bitwise_count(m)
+    mu_m = np.zeros(1 << inst.N)
+    for u in range(inst.N):
+        mu_m += inst.nu[u] * ((m >> u) & 1)
+    return inst, pop, mu_m
+
+
+def _sample_layer(rng, N, n, k):
+    out = np.empty(k, dtype=np.uint32)
+    for i in range(k):
+        bits = rng.choice(N, n, replace=False)
+        out[i] = np.sum(np.left_shift(np.uint32(1), bits.astype(np.uint32)))
+    return out
+
+
+def test_full_size_layer_update(big):
+    inst, pop, mu_m = big
+    N, Lam = inst.N, inst.Lambda
+    say("case N=26 layer update: iterate")
+    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE)
+    hq.hq_iterate(ctx, 2)
+    S1 = hq.hq_conditional(ctx)
+    hq.hq_iterate(ctx, 1)
+    S2 = hq.hq_conditional(ctx)
+    rng = np.random.default_rng(0)
+
+    def lam_of(S, n):
+        return 0.0 if n == N else Lam * S[pop == n].sum()
+
+    def mu_of(S, n):
+        return float((mu_m[pop == n] * S[pop == n]).sum())
+
+    for n in (1, 3, 9, 13, 17, 20, 24, 25):
+        say(f"case N=26 layer {n}")
+        alpha = mu_of(S1, n) / lam_of(S2, n - 1)  # mu^2(n) / lambda^3(n-1)
+        beta = lam_of(S1, n) / mu_of(S1, n + 1)   # lambda^2(n) / mu^2(n+1)
+        states = _sample_layer(rng, N, n, 1500)
+        want, _, _ = cpu.update_states(inst, states, S2, S1, alpha, beta)
+        got = S2[states]
+        rel = np.abs(got - want) / np.abs(want)
+        assert rel.max() <= 1e-11, (n, rel.max())
+
+
+def test_full_size_converged_balance_and_marginals(big):
+    inst, pop, mu_m = big
+    say("case N=26 solve to 1e-8")
+    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE)
+    info = hq.hq_solve(ctx, 1e-8)
+    assert info["residual"] <= 1e-8
+    P = hq.hq_state(ctx)
+    assert abs(P.sum() - 1.0) < 1e-12 and P.min() >= 0.0
+    rng = np.random.default_rng(1)
+    # sampled balance terms, weighted towards the likely states
+    states = np.unique(np.r_[rng.integers(0, 1 << inst.N, 20000).astype(np.uint32),
+                             rng.choice(1 << inst.N, 20000, p=P).astype(np.uint32)])
+    terms, out = cpu.balance_terms(inst, states, P)
+    ratio = np.abs(terms).sum() / out.sum()
+    say(f"  sampled balance ratio {ratio:.3e} (GPU residual {info['residual']:.3e})")
+    assert ratio <= 20 * 1e-8
+    rho, pn = hq.hq_marginals(ctx)
+    rr, rp = cpu.marginals(inst.N, P)
+    np.testing.assert_allclose(rho, rr, rtol=1e-9)
+    np.testing.assert_allclose(pn, rp, rtol=1e-9, atol=1e-300)
+    # flow balance per unit: sum_u nu_u rho_u = Lambda (1 - P(full))
+    assert (inst.nu * rho).sum() == pytest.approx(inst.Lambda * (1 - P[-1]), rel=1e-7)
