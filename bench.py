@@ -27,6 +27,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 L1 residual & state-updates/s at N=26; warm/batched vs plain"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_03019_amd", "csrc", "hq_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(N: int, precision: str):
+    """HBM bytes per outer iteration of the layer kernels, from the committed
+    counter summary; None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"layer_kernel_n{N}_{precision}_hbm_bytes.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_iteration"])
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_bytes_per_iteration(N: int, s: int) -> float:
@@ -35,7 +63,15 @@ def algorithmic_bytes_per_iteration(N: int, s: int) -> float:
     return float(s * sum(C(N, n - 1) + C(N, n) + C(N, n + 1) for n in range(1, N)))
 
 
-def cpu_baseline(inst, seconds_target: float = 12.0):
+def _sample_layer_states(rng, N: int, n: int, k: int):
+    """k uniformly drawn states of layer n (n of the N bits set)."""
+    import numpy as np
+
+    bits = np.argsort(rng.random((k, N)), axis=1)[:, :n].astype(np.uint32)
+    return np.bitwise_or.reduce(np.left_shift(np.uint32(1), bits), axis=1).astype(np.uint32)
+
+
+def cpu_baseline(inst, seconds_target: float = 15.0):
     import numpy as np
 
     from oracle import cpu
@@ -48,30 +84,132 @@ def cpu_baseline(inst, seconds_target: float = 12.0):
     # neighbour layers: any positive values (the timing does not depend on them)
     pl = rng.random(S)
     pu = pl
-    # states of the middle layer, sampled uniformly
-    def sample(k):
-        out = np.empty(k, dtype=np.uint32)
-        for i in range(k):
-            bits = rng.choice(N, n, replace=False)
-            out[i] = int(sum(1 << int(b) for b in bits))
-        return out
-
-    probe = sample(2000)
+    probe = _sample_layer_states(rng, N, n, 20000)
     t = time.perf_counter()
     cpu.update_states(inst, probe, pl, pu, 1.0, 1.0)
     dt = max(time.perf_counter() - t, 1e-6)
-    k = int(min(2_000_000, max(2000, 2000 * seconds_target / dt)))
-    states = sample(k) if k <= 200_000 else np.resize(sample(200_000), k)
+    chunk = int(min(4_000_000, max(20000, 20000 * 2.0 / dt)))  # about 2 s per call
+    states = _sample_layer_states(rng, N, n, chunk)
+    k = 0
     t = time.perf_counter()
-    cpu.update_states(inst, states, pl, pu, 1.0, 1.0)
-    dt = time.perf_counter() - t
+    while True:
+        cpu.update_states(inst, states, pl, pu, 1.0, 1.0)
+        k += chunk
+        dt = time.perf_counter() - t
+        if dt >= seconds_target:
+            break
     return {
         "value": k / dt,
         "unit": "state-updates/s",
         "cores": cpu.threads(),
         "kind": "oracle",
-        "sample": f"one update (12) of {k} sampled layer-{n} states of the same N={N} instance, "
-                  f"Algorithm-3 coefficients generated per state; {dt:.1f} s",
+        "sample": f"one update (12) of {k} uniformly sampled layer-{n} states of the same N={N}, "
+                  f"J={inst.J} instance (Algorithm-3 coefficients generated per state), {dt:.1f} s "
+                  f"on {cpu.threads()} threads",
+    }
+
+
+def copy_probe(mib: int, reps: int):
+    """A plain device copy of known size (calibrates the HBM byte counters)."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "reps": reps}), flush=True)
+
+
+def batched_leg(hq, config_instance, tol: float, count: int = 256):
+    """The batch of uneven deployments in one persistent launch vs one plain
+    solve after the other (same contexts, same tolerance)."""
+    import torch
+
+    insts = [config_instance(4, i) for i in range(count)]
+    ctxs = [hq.create_from_instance(i, inner=hq.HQ_INNER_ONE) for i in insts]
+    hq.hq_solve_batch(ctxs, tol)  # first call: tile autotune and graph capture
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, infos = hq.hq_solve_batch(ctxs, tol)
+    batch_s = time.perf_counter() - t
+    t = time.perf_counter()
+    seq = [hq.hq_solve(c, tol) for c in ctxs]
+    seq_s = time.perf_counter() - t
+    updates = sum(((1 << i.N) - 2) * x["iterations"] for i, x in zip(insts, infos))
+    for c in ctxs:
+        hq.hq_destroy(c)
+    return {
+        "workload": f"{count} deployments, N~U{{12..18}} (total {sum(1 << i.N for i in insts)} states), "
+                    f"J=100 uniform, mu_i~U[0.8,1.2], load 0.6, tol {tol:g}",
+        "batched_s": batch_s,
+        "sequential_s": seq_s,
+        "speedup_vs_sequential": seq_s / batch_s,
+        "state_updates_per_s": updates / batch_s,
+        "iterations_mean": sum(x["iterations"] for x in infos) / count,
+        "max_residual": max(x["residual"] for x in infos),
+        "sequential_max_residual": max(x["residual"] for x in seq),
+    }
+
+
+def warm_leg(hq, inst, tol: float, plain_s: float, plain_iters: float, steps: int):
+    """Learned product-form start (shipped network) on the same instance;
+    the timed region also covers feature extraction and inference."""
+    import torch
+
+    from paper_2603_03019_amd import warmstart
+
+    net = warmstart.load_network()
+    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE, mlp=net)
+    hq.hq_solve(ctx, tol)
+    torch.cuda.synchronize()
+    total, iters, kept, res = 0.0, 0, 0, 0.0
+    for _ in range(steps):
+        t = time.perf_counter()
+        X = hq.hq_mlp_features(inst.N, inst.J, inst.lam, inst.nu, inst.pref)
+        hq.hq_mlp_forward(net, X)
+        info = hq.hq_solve(ctx, tol)
+        total += time.perf_counter() - t
+        iters += info["iterations"]
+        kept += info["warm_used"]
+        res = max(res, info["residual"])
+    hq.hq_destroy(ctx)
+    hq.hq_mlp_destroy(net)
+    return {
+        "time_to_tol_s": total / steps,
+        "iterations": iters / steps,
+        "plain_time_to_tol_s": plain_s,
+        "plain_iterations": plain_iters,
+        "speedup_vs_plain": plain_s / (total / steps),
+        "warm_start_kept": kept / steps,
+        "final_residual": res,
+    }
+
+
+def fp32_leg(hq, inst, tol: float, P64, steps: int):
+    """FP32 storage with per-layer scales (FP64 reductions), handed to FP64
+    at the FP32 floor; error of the result against the FP64 solve."""
+    import numpy as np
+    import torch
+
+    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE, precision=hq.HQ_FP32_POLISH64)
+    hq.hq_solve(ctx, tol)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    infos = [hq.hq_solve(ctx, tol) for _ in range(steps)]
+    wall = (time.perf_counter() - t) / steps
+    P = hq.hq_state(ctx)
+    hq.hq_destroy(ctx)
+    it = infos[-1]
+    return {
+        "time_to_tol_s": wall,
+        "iterations": it["iterations"],
+        "fp64_iterations": it["fp64_iterations"],
+        "sweep_state_updates_per_s": ((1 << inst.N) - 2) * it["iterations"] / max(it["sweep_seconds"], 1e-12),
+        "final_residual": it["residual"],
+        "l1_vs_fp64": float(np.abs(P - P64).sum()),
     }
 
 
@@ -87,6 +225,11 @@ def main():
     ap.add_argument("--inner", choices=["closed", "one"], default="one")
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the batched, warm and FP32 forms")
+    ap.add_argument("--profile-iters", type=int, default=0,
+                    help="only set up and run this many outer iterations (for counter runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
+                    help="only run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not "
@@ -99,6 +242,9 @@ def main():
     from paper_2603_03019_amd.instances import config_instance
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, 4)
+        return
     inst = config_instance(3, 0, N=args.N, J=args.J)
     prec = {"fp64": hq.HQ_FP64, "fp32": hq.HQ_FP32, "polish": hq.HQ_FP32_POLISH64}[args.precision]
     inner = hq.HQ_INNER_ONE if args.inner == "one" else hq.HQ_INNER_CLOSED
@@ -106,6 +252,13 @@ def main():
     t = time.perf_counter()
     ctx = hq.create_from_instance(inst, precision=prec, inner=inner, tile_bits=args.tile_bits, device=0)
     create_s = time.perf_counter() - t
+    if args.profile_iters:
+        hq.hq_iterate(ctx, args.profile_iters)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_iters": args.profile_iters, "N": inst.N,
+                          "bytes_per_iteration": algorithmic_bytes_per_iteration(
+                              inst.N, 8 if args.precision == "fp64" else 4)}), flush=True)
+        return
     for i in range(args.warmup):
         info = hq.hq_solve(ctx, args.tol)
         print(f"bench: warmup {i} iterations={info['iterations']} residual={info['residual']:.3e} "
@@ -127,7 +280,6 @@ def main():
     passes = 2 if args.inner == "closed" else 1
     per_it = sweep_s / max(iters, 1)
     achieved = bytes_it / per_it / 1e9
-    rho, pn = hq.hq_marginals(ctx)
     out = {
         "metric": METRIC,
         "value": states * iters / wall,
@@ -159,13 +311,27 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(inst.N, args.precision),
             "kernel": f"layer_kernel (M_WRITE{' + M_PASS1' if passes == 2 else ''}), per outer iteration "
                       f"of {inst.N - 1} layer launches",
             "bytes_per_iteration": bytes_it,
             "us_per_iteration": per_it * 1e6,
         },
     }
+    if not args.no_legs and args.precision == "fp64":
+        plain_s, plain_iters = wall / args.steps, iters / args.steps
+        P64 = hq.hq_state(ctx)
+        hq.hq_destroy(ctx)
+        print("bench: fp32 form", flush=True)
+        out["fp32_form"] = fp32_leg(hq, inst, args.tol, P64, 1)
+        del P64
+        from paper_2603_03019_amd import warmstart
+
+        if os.path.exists(warmstart.WEIGHTS):
+            print("bench: warm start", flush=True)
+            out["warm_start"] = warm_leg(hq, inst, args.tol, plain_s, plain_iters, 1)
+        print("bench: batched form", flush=True)
+        out["batched"] = batched_leg(hq, config_instance, args.tol)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", flush=True)
         out["cpu_baseline"] = cpu_baseline(inst)

@@ -15,6 +15,9 @@ network's forward/backward/Adam kernels); this module only orchestrates.
 """
 from __future__ import annotations
 
+import argparse
+import json
+import os
 import time
 from typing import Dict, List, Optional
 
@@ -22,6 +25,16 @@ import numpy as np
 
 from . import hq
 from .instances import config_instance
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warm_mlp.npy")
+
+
+def load_network(path: str = WEIGHTS, device: int = -1):
+    """The shipped network (FP32 master parameters written by ``main``)."""
+    params = np.load(path, allow_pickle=False)
+    m = hq.hq_mlp_create(device=device, seed=0)
+    hq.hq_mlp_set_params(m, params)
+    return m
 
 
 def training_set(count: int, *, first_index: int = 1000, tol: float = 1e-7, chunk: int = 512,
@@ -103,3 +116,38 @@ def summarize(res: Dict[str, list]) -> dict:
     s["warm_kept_fraction"] = float(np.mean(res["warm_kept"]))
     s["instances"] = len(res["N"])
     return s
+
+
+def main(argv=None):
+    """Train the shipped network on method-generated solves and evaluate it.
+
+    python -m paper_2603_03019_amd.warmstart --train 4096 --eval 100
+    """
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=4096, help="training deployments to solve")
+    ap.add_argument("--eval", type=int, default=100, help="unseen N=24 deployments to evaluate")
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--summary", default="")
+    a = ap.parse_args(argv)
+    t = time.perf_counter()
+    X, y = training_set(a.train, verbose=True)
+    print(f"warmstart: {X.shape[0]} rows from {a.train} solves in {time.perf_counter() - t:.1f}s", flush=True)
+    t = time.perf_counter()
+    net, losses = train(X, y, epochs=a.epochs)
+    print(f"warmstart: trained in {time.perf_counter() - t:.1f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}",
+          flush=True)
+    os.makedirs(os.path.dirname(a.out), exist_ok=True)
+    np.save(a.out, hq.hq_mlp_get_params(net).astype(np.float32), allow_pickle=False)
+    s = {"train_solves": a.train, "train_rows": int(X.shape[0]), "epochs": a.epochs,
+         "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+    if a.eval:
+        s.update(summarize(evaluate(net, range(50000, 50000 + a.eval), verbose=True)))
+    print(json.dumps(s), flush=True)
+    if a.summary:
+        with open(a.summary, "w") as f:
+            json.dump(s, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
