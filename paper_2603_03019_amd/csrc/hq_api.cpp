@@ -11,7 +11,10 @@
 #include <mutex>
 #include <memory>
 #include <new>
+#include <stdexcept>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "hq.h"
@@ -108,8 +111,10 @@ struct hq_ctx {
     float* x32 = nullptr;
     double *d_nu = nullptr, *d_mu_lo = nullptr, *d_tcoef = nullptr, *d_scal = nullptr, *d_part = nullptr;
     double *d_scale64 = nullptr, *d_scale32 = nullptr, *d_rho = nullptr, *d_xu = nullptr, *d_given = nullptr;
-    uint32_t *d_binom = nullptr, *d_layer_off = nullptr, *d_lo_qstart = nullptr, *d_ent_off = nullptr,
-             *d_ent_list = nullptr, *d_orig_bit = nullptr, *d_seg_desc = nullptr, *d_segoff = nullptr;
+    uint32_t *d_binom = nullptr, *d_layer_off = nullptr, *d_lo_qstart = nullptr, *d_prog_off = nullptr,
+             *d_orig_bit = nullptr, *d_seg_desc = nullptr, *d_segoff = nullptr;
+    ProgTerm* d_prog = nullptr;
+    size_t prog_terms = 0;
     double* d_coefs = nullptr;
     int stored_from = -1;  // first layer with stored coefficients (-1: none)
     uint16_t *d_lo_unrank = nullptr, *d_lo_rank = nullptr;
@@ -125,7 +130,7 @@ struct hq_ctx {
     void release() {
         void* ptrs[] = {x64,       x32,        d_nu,       d_mu_lo,    d_tcoef,     d_scal,     d_part,
                         d_scale64, d_scale32,  d_rho,      d_xu,       d_given,     d_binom,    d_layer_off,
-                        d_lo_qstart, d_ent_off, d_ent_list, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
+                        d_lo_qstart, d_prog_off, d_prog, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
                         d_counters, d_seg_desc, d_segoff,   d_coefs};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
@@ -234,52 +239,130 @@ std::vector<TrieNode> build_trie(int N, int J, const double* lam, const std::vec
     return nodes;
 }
 
-// Per-tile part of the dispatch walk.  For tile T (high units busy iff
-// their bit is set), walk the trie through busy high units: their rates are
-// uniform over the tile's states (tcoef[T][u]).  A low unit l ends the
-// uniform walk: its rate is credited per lane iff l is busy (tcoef[T][l]),
-// and the node (an "entry") is listed under l so that its subtree is walked
-// per lane, and skipped outright when no lane has l busy.
-void build_tiles(int N, int b, const std::vector<TrieNode>& nodes, std::vector<double>& tcoef,
-                 std::vector<uint32_t>& ent_off, std::vector<uint32_t>& ents) {
-    const int H = N - b;
-    const uint32_t tiles = 1u << H;
-    tcoef.assign((size_t)tiles * N, 0.0);
-    ent_off.assign((size_t)tiles * b + 1, 0);
-    ents.clear();
-    const uint32_t nn = (uint32_t)nodes.size();
-    std::vector<std::vector<uint32_t>> group(b);
-    for (uint32_t T = 0; T < tiles; ++T) {
-        double* tc = tcoef.data() + (size_t)T * N;
-        for (auto& g : group) g.clear();
-        const uint32_t Tabs = T << b;
-        uint32_t i = 0;
-        while (i < nn) {
-            const TrieNode& nd = nodes[i];
-            const int u = (int)(nd.skip_unit & 31u);
-            const uint32_t sk = nd.skip_unit >> 5;
-            if (u >= b) {
-                if ((Tabs >> u) & 1u) {
-                    tc[u] += nd.rate;
-                    ++i;
-                } else {
-                    i = sk;
-                }
+// Dispatch credits of Algorithm 3 as merged terms.  Node j credits
+// lambda_j to its h-th unit iff that unit and every unit ranked before it
+// are busy; with u in m already required by the up-sum of (12), the term
+// is (cond = units ranked before u, u, lambda_j).  Terms with the same
+// (cond, u) are summed.
+struct Term {
+    uint32_t cond;
+    int unit;
+    double rate;
+};
+
+std::vector<Term> build_terms(int N, int J, const double* lam, const std::vector<int32_t>& rp) {
+    std::unordered_map<uint64_t, size_t> index;
+    std::vector<Term> terms;
+    for (int j = 0; j < J; ++j) {
+        if (!(lam[j] > 0.0)) continue;
+        uint32_t cond = 0;
+        for (int h = 0; h < N; ++h) {
+            const int u = rp[(size_t)j * N + h];
+            const uint64_t key = ((uint64_t)u << 32) | cond;
+            auto it = index.find(key);
+            if (it == index.end()) {
+                index.emplace(key, terms.size());
+                terms.push_back(Term{cond, u, lam[j]});
             } else {
-                tc[u] += nd.rate;
-                if (sk > i + 1) group[u].push_back(i);
-                i = sk;
+                terms[it->second].rate += lam[j];
             }
-        }
-        for (int l = 0; l < b; ++l) {
-            ent_off[(size_t)T * b + l] = (uint32_t)(ents.size() / 2);
-            for (uint32_t e : group[l]) {
-                ents.push_back(e + 1);                        // first child
-                ents.push_back(nodes[e].skip_unit >> 5);      // end of the subtree
-            }
+            cond |= 1u << u;
         }
     }
-    ent_off[(size_t)tiles * b] = (uint32_t)(ents.size() / 2);
+    // deterministic order: by unit, then condition
+    std::sort(terms.begin(), terms.end(), [](const Term& a, const Term& b) {
+        return a.unit != b.unit ? a.unit < b.unit : a.cond < b.cond;
+    });
+    return terms;
+}
+
+// Per-tile dispatch tables.  For tile T (high units busy iff their bit is
+// set) a term applies to the tile's states iff its high condition bits lie
+// in T.  Terms with no low condition bits are uniform over the tile and are
+// summed into tcoef[T][u]; the others are merged by (low mask, unit) into
+// the tile's program, grouped by unit: prog_off[T * (N+1) + u] is the first
+// term of unit u, prog_off[T * (N+1) + N] the end.  A high unit that is idle
+// in T never needs its coefficient and gets no terms.
+void build_programs(int N, int b, const std::vector<Term>& terms, std::vector<double>& tcoef,
+                    std::vector<uint32_t>& prog_off, std::vector<ProgTerm>& prog) {
+    const int H = N - b;
+    const uint32_t tiles = 1u << H;
+    const uint32_t lomask = (1u << b) - 1u;
+    tcoef.assign((size_t)tiles * N, 0.0);
+    prog_off.assign((size_t)tiles * (N + 1), 0);
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (tiles < 64) nth = 1;
+    std::vector<std::vector<ProgTerm>> part(nth);
+    std::vector<std::vector<uint32_t>> counts(nth);  // per tile and unit, within the part
+    auto work = [&](unsigned w) {
+        const uint32_t t0 = (uint32_t)((uint64_t)tiles * w / nth), t1 = (uint32_t)((uint64_t)tiles * (w + 1) / nth);
+        std::vector<ProgTerm>& out = part[w];
+        std::vector<uint32_t>& cnt = counts[w];
+        cnt.assign((size_t)(t1 - t0) * N, 0);
+        std::vector<std::pair<uint32_t, double>> cur;  // (low mask, rate) of one unit
+        for (uint32_t T = t0; T < t1; ++T) {
+            double* tc = tcoef.data() + (size_t)T * N;
+            size_t i = 0;
+            while (i < terms.size()) {
+                const int u = terms[i].unit;
+                size_t e = i;
+                while (e < terms.size() && terms[e].unit == u) ++e;
+                const bool needed = u < b || ((T >> (u - b)) & 1u);
+                cur.clear();
+                for (size_t k = i; k < e && needed; ++k) {
+                    const uint32_t hi = terms[k].cond >> b, lo = terms[k].cond & lomask;
+                    if (hi & ~T) continue;
+                    if (lo == 0) {
+                        tc[u] += terms[k].rate;
+                    } else {
+                        cur.emplace_back(lo, terms[k].rate);
+                    }
+                }
+                if (!cur.empty()) {
+                    std::stable_sort(cur.begin(), cur.end(),
+                                     [](const std::pair<uint32_t, double>& a, const std::pair<uint32_t, double>& b) {
+                                         return a.first < b.first;
+                                     });
+                    uint32_t c = 0;
+                    for (size_t k = 0; k < cur.size(); ++k) {
+                        if (k > 0 && cur[k].first == cur[k - 1].first) {
+                            out.back().rate += cur[k].second;
+                        } else {
+                            out.push_back(ProgTerm{cur[k].first, 0u, cur[k].second});
+                            ++c;
+                        }
+                    }
+                    cnt[(size_t)(T - t0) * N + u] = c;
+                }
+                i = e;
+            }
+        }
+    };
+    if (nth == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nth; ++w) th.emplace_back(work, w);
+        for (auto& t : th) t.join();
+    }
+    size_t total = 0;
+    for (auto& v : part) total += v.size();
+    if (total >= 0xffffffffull) throw std::length_error("dispatch program too large");
+    prog.clear();
+    prog.reserve(total);
+    uint32_t pos = 0;
+    for (unsigned w = 0; w < nth; ++w) {
+        const uint32_t t0 = (uint32_t)((uint64_t)tiles * w / nth), t1 = (uint32_t)((uint64_t)tiles * (w + 1) / nth);
+        for (uint32_t T = t0; T < t1; ++T) {
+            for (int u = 0; u < N; ++u) {
+                prog_off[(size_t)T * (N + 1) + u] = pos;
+                pos += counts[w][(size_t)(T - t0) * N + u];
+            }
+            prog_off[(size_t)T * (N + 1) + N] = pos;
+        }
+        prog.insert(prog.end(), part[w].begin(), part[w].end());
+        std::vector<ProgTerm>().swap(part[w]);
+    }
 }
 
 void setup_params(hq_ctx* c) {
@@ -298,8 +381,8 @@ void setup_params(hq_ctx* c) {
     P.tcoef = c->d_tcoef;
     P.seg_desc = c->d_seg_desc;
     P.segoff = c->d_segoff;
-    P.ent_off = c->d_ent_off;
-    P.ent_range = reinterpret_cast<const uint2*>(c->d_ent_list);
+    P.prog_off = c->d_prog_off;
+    P.prog = c->d_prog;
     P.nodes = c->d_nodes;
     P.coefs = c->d_coefs;
     const int L = c->N + 1;
@@ -387,8 +470,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
 
     c->nodes = build_trie(N, J, lam, rp);
     std::vector<double> tcoef;
-    std::vector<uint32_t> ent_off, ents;
-    build_tiles(N, b, c->nodes, tcoef, ent_off, ents);
+    std::vector<uint32_t> prog_off;
+    std::vector<ProgTerm> prog;
+    build_programs(N, b, build_terms(N, J, lam, rp), tcoef, prog_off, prog);
+    c->prog_terms = prog.size();
 
     // layout tables (hq_layout.h)
     hqlayout::Layout lay;
@@ -480,8 +565,8 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->d_binom = dalloc<uint32_t>(tb.size());
         c->d_layer_off = dalloc<uint32_t>(layer_off.size());
         c->d_lo_qstart = dalloc<uint32_t>(lo_qstart.size());
-        c->d_ent_off = dalloc<uint32_t>(ent_off.size());
-        c->d_ent_list = dalloc<uint32_t>(ents.size());
+        c->d_prog_off = dalloc<uint32_t>(prog_off.size());
+        c->d_prog = dalloc<ProgTerm>(std::max<size_t>(prog.size(), 1));
         c->d_seg_desc = dalloc<uint32_t>(seg_desc.size());
         c->d_segoff = dalloc<uint32_t>(segoff.size());
         c->d_coefs = dalloc<double>(coef_total);
@@ -499,8 +584,8 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         h2d(c->d_binom, tb, s);
         h2d(c->d_layer_off, layer_off, s);
         h2d(c->d_lo_qstart, lo_qstart, s);
-        h2d(c->d_ent_off, ent_off, s);
-        h2d(c->d_ent_list, ents, s);
+        h2d(c->d_prog_off, prog_off, s);
+        if (!prog.empty()) h2d(c->d_prog, prog, s);
         h2d(c->d_seg_desc, seg_desc, s);
         h2d(c->d_segoff, segoff, s);
         h2d(c->d_orig_bit, orig_bit, s);
@@ -1013,6 +1098,8 @@ hq_status hq_create(int N, int J, const double* lambda_j, const double* mu_i, co
         return create_impl(N, J, lambda_j, mu_i, pref_lists, opts, out);
     } catch (const std::bad_alloc&) {
         return fail(HQ_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (const std::length_error&) {
+        return fail(HQ_ERR_OUT_OF_MEMORY, "per-tile dispatch programs exceed 2^32 terms");
     } catch (const HipError& e) {
         return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
     } catch (...) {

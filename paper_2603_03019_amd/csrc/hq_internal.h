@@ -14,6 +14,16 @@
 #endif
 #define HQ_GRID 2048        // persistent work-groups per layer launch (8 per CU)
 
+// One term of a tile's dispatch program: unit u (given by the group the
+// term sits in) gains `rate` in every state of the tile whose low bits
+// contain `mask` (the low units ranked before u by the demand nodes summed
+// into the term).
+struct ProgTerm {
+    uint32_t mask;
+    uint32_t pad;
+    double rate;
+};
+
 // One node of the merged preference trie, in preorder.  A node stands for
 // a preference prefix shared by one or more demand nodes; `rate` is the
 // summed arrival rate of those demand nodes.  `need` is the set of units on
@@ -57,8 +67,8 @@ struct SweepParams {
     const double* tcoef;         // [2^H * N] per-tile dispatch coefficients
     const uint32_t* seg_desc;    // per layer and work-group: (T << 4) | q
     const uint32_t* segoff;      // [(b+1) * 2^H] absolute start of segment (T, q)
-    const uint32_t* ent_off;     // [2^H * b + 1] per tile, per low unit: trie entries below it
-    const uint2* ent_range;      // per entry: the node range [first child, end of subtree)
+    const uint32_t* prog_off;    // [2^H * (N+1)] per tile: first program term of unit u, and the end
+    const ProgTerm* prog;        // per-tile dispatch programs, grouped by unit
     const TrieNode* nodes;
     const double* coefs;         // stored coefficients of the top layers (unit-major per layer)
     const double* scale;         // [N+1] storage scale of each layer (x = scale * p)

@@ -13,11 +13,14 @@
 // and are found through a 2^b rank table held in LDS.
 //
 // Dispatch.  The arrival coefficient a(m, u) of eq. (3) / Algorithm 3 is
-// evaluated on the fly from a merged preference trie.  Units are relabelled
-// on the host so that the low (per-lane) bits are the units that demand
-// nodes rank late; the part of the trie walk that depends only on T is
-// precomputed per tile (tcoef), and only the remainder below a low unit is
-// walked here, wave-uniformly, with per-lane subset tests.
+// evaluated on the fly.  The host merges the credits of all demand nodes
+// into terms (units ranked before u, u, rate) and, per tile T, splits them:
+// terms whose condition involves no low unit are uniform over the tile
+// (tcoef), the rest form a short per-tile program of (low mask, rate)
+// pairs grouped by unit.  Units are relabelled so that the low (per-lane)
+// bits go to the units that demand nodes rank late, which keeps those
+// programs short.  Per state the coefficient of a busy unit is then a few
+// predicated adds, with no data-dependent memory access.
 //
 // Each kernel ends with a deterministic two-level FP64 reduction: wave
 // shuffles, one partial per work-group, and a fixed-order sum by the last
@@ -202,120 +205,163 @@ __device__ __forceinline__ ModeScalars mode_scalars(const SweepParams& P, int n,
     return ms;
 }
 
+// Wave-uniform values are fetched lane-parallel (lane i loads entry i of a
+// small per-segment record with one vector load) and broadcast with
+// readlane where they are used.  This keeps them out of scalar registers
+// and costs one memory round trip per record instead of a chain of scalar
+// loads.
+__device__ __forceinline__ uint32_t bcast(uint32_t v, uint32_t i) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)i);
+}
+__device__ __forceinline__ double bcast(double v, uint32_t i) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = bcast((uint32_t)b, i), hi = bcast((uint32_t)(b >> 32), i);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Up to HQ_PROG_REG program terms of a tile are held in registers, the rest
+// are read as scalar loads.
+#define HQ_PROG_REG 128
+
+struct SegRecord {
+    uint32_t seg;   // lane k < H: start of segment (T xor e_k, q); lane H, H+1, H+2: (T, q-1), (T, q+1), (T, q)
+    uint32_t po;    // lane u <= N: prog_off[T][u]
+    double tc;      // lane u < N: tcoef[T][u]
+    uint32_t pm0, pm1;  // program terms 0..63 and 64..127 of the tile: masks
+    double pr0, pr1;    //   and rates
+};
+
+__device__ __forceinline__ SegRecord load_record(const SweepParams& P, int b, int H, int q, uint32_t Tb,
+                                                 bool stored) {
+    const int lane = threadIdx.x & 63;
+    const int N = P.N;
+    const uint32_t tiles = 1u << H;
+    SegRecord r;
+    r.seg = 0u;
+    if (lane < H)
+        r.seg = P.segoff[hqlayout::seg_index(q, Tb ^ (1u << lane), tiles)];
+    else if (lane == H)
+        r.seg = hqlayout::low_down_segment(P.segoff, tiles, q, Tb);
+    else if (lane == H + 1)
+        r.seg = hqlayout::low_up_segment(P.segoff, tiles, q, b, Tb);
+    else if (lane == H + 2)
+        r.seg = P.segoff[hqlayout::seg_index(q, Tb, tiles)];
+    r.po = 0u;
+    r.tc = 0.0;
+    r.pm0 = r.pm1 = 0u;
+    r.pr0 = r.pr1 = 0.0;
+    if (stored) return r;
+    if (lane <= N) r.po = P.prog_off[(size_t)Tb * (N + 1) + lane];
+    if (lane < N) r.tc = P.tcoef[(size_t)Tb * N + lane];
+    const uint32_t p0 = bcast(r.po, 0u), nt = bcast(r.po, (uint32_t)N) - p0;
+    if ((uint32_t)lane < nt) {
+        const ProgTerm t = P.prog[p0 + lane];
+        r.pm0 = t.mask;
+        r.pr0 = t.rate;
+    }
+    if (nt > 64u && (uint32_t)lane + 64u < nt) {
+        const ProgTerm t = P.prog[p0 + 64u + lane];
+        r.pm1 = t.mask;
+        r.pr1 = t.rate;
+    }
+    return r;
+}
+
+// Arrival coefficient of busy unit u for the lane's low pattern L: the
+// tile-uniform part plus the unit's program terms whose mask lies in L.
+__device__ __forceinline__ double unit_coef(const SweepParams& P, const SegRecord& r, int u, uint32_t L) {
+    double c = bcast(r.tc, (uint32_t)u);
+    const uint32_t p0 = bcast(r.po, 0u);
+    const uint32_t i0 = bcast(r.po, (uint32_t)u) - p0, i1 = bcast(r.po, (uint32_t)u + 1u) - p0;
+    for (uint32_t i = i0; i < i1; ++i) {
+        uint32_t mk;
+        double rt;
+        if (i < 64u) {
+            mk = bcast(r.pm0, i);
+            rt = bcast(r.pr0, i);
+        } else if (i < HQ_PROG_REG) {
+            mk = bcast(r.pm1, i - 64u);
+            rt = bcast(r.pr1, i - 64u);
+        } else {
+            const HQ_CONST ProgTerm* t = ro(P.prog) + p0 + i;
+            mk = t->mask;
+            rt = t->rate;
+        }
+        c += ((L & mk) == mk) ? rt : 0.0;
+    }
+    return c;
+}
+
 // One wave updates (or, for M_RESID / M_PASS1, evaluates) the states of
 // segment `si` of layer A.n; accumulates the layer sums in acc0..acc2.
-template <typename T, int MODE, bool TRACK_DELTA, bool STORED>
+// Every state reads its N neighbours once, all loads issued together; the
+// arrival coefficient of busy unit u is tcoef[T][u] plus the lane's terms
+// of the tile program of u (or, with STORED, the stored a(m, u)).
+// BF, HF: the tile shape (low bits b, high bits H) fixed at compile time,
+// or 0 to take it from P.  With a fixed shape the unrolled per-unit code
+// needs no run-time guards, which keeps the register budget at 4 waves per
+// SIMD.
+template <typename T, int MODE, bool TRACK_DELTA, bool STORED, int BF = 0, int HF = 0>
 __device__ __forceinline__ void segment_update(const SweepParams& P, const LayerArgs& A, T* __restrict__ x,
                                                uint32_t si, const uint16_t* s_rank, const uint16_t* s_unrank,
                                                const uint32_t* s_qstart, const ModeScalars& ms, double& acc0,
                                                double& acc1, double& acc2) {
+    constexpr int MAXB = BF ? BF : HQ_MAXB, MAXH = HF ? HF : HQ_MAXH;
     const int lane = threadIdx.x & 63;
-    const int n = A.n, b = P.b, H = P.H, N = P.N;
-    const uint32_t tiles = 1u << H;
+    const int n = A.n, N = P.N;
+    const int b = BF ? BF : P.b, H = HF ? HF : P.H;
     const uint32_t full = (N >= 32) ? 0xffffffffu : ((1u << N) - 1u);
     const HQ_CONST double* nuc = ro(P.nu);
-    const uint32_t layer0 = ro(P.layer_off)[n];
     const double alpha = ms.alpha, beta = ms.beta, pdn = ms.pdn, pself = ms.pself, pup = ms.pup;
     const double is_dn = ms.is_dn, is_up = ms.is_up, s_self = ms.s_self, is_self = ms.is_self;
     const uint32_t d = ro(P.seg_desc)[A.desc_base + si];
     const int q = (int)(d & 15u);
     const uint32_t Tb = d >> 4;
-    // neighbour segments, wave-uniform: (T xor k, q) for high unit k,
-    // (T, q - 1) / (T, q + 1) for low units, and the segment itself
-    uint32_t off[HQ_MAXH];
-#pragma unroll
-    for (int k = 0; k < HQ_MAXH; ++k)
-        if (k < H) off[k] = hqlayout::high_neighbour(ro(P.segoff), tiles, q, Tb, k, 0u);
-    const uint32_t offDlo = hqlayout::low_down_segment(ro(P.segoff), tiles, q, Tb);
-    const uint32_t offUlo = hqlayout::low_up_segment(ro(P.segoff), tiles, q, b, Tb);
-    const uint32_t offSelf = ro(P.segoff)[hqlayout::seg_index(q, Tb, tiles)];
+    const SegRecord r = load_record(P, b, H, q, Tb, STORED);
+    const uint32_t offDlo = bcast(r.seg, (uint32_t)H), offUlo = bcast(r.seg, (uint32_t)H + 1u);
+    const uint32_t offSelf = bcast(r.seg, (uint32_t)H + 2u);
     double mu_hi = 0.0;
     for (int k = 0; k < H; ++k)
         if ((Tb >> k) & 1u) mu_hi += nuc[b + k];
     const uint32_t cnt = ro(P.binom)[b * 32 + q];
-    const uint32_t rank0 = offSelf - layer0;
-    const HQ_CONST uint32_t* eo = ro(P.ent_off) + (size_t)Tb * b;
-    const double* cs = P.coefs + A.coef_base + rank0;
-    const HQ_CONST double* tcT = ro(P.tcoef) + (size_t)Tb * N;  // this tile's dispatch rates
+    const double* cs = P.coefs + A.coef_base + (offSelf - ro(P.layer_off)[n]);
     const uint32_t qs = s_qstart[q];
     const uint32_t Tabs = Tb << b;
 
     for (uint32_t t = lane; t < cnt; t += 64) {
         const uint32_t L = s_unrank[qs + t];
         const uint32_t m = Tabs | L;
+        // every neighbour value first: low units in the small segments
+        // (T, q -+ 1), high units segment-aligned and coalesced
+        double vl[MAXB], vh[MAXH];
+#pragma unroll
+        for (int l = 0; l < MAXB; ++l)
+            if (l < b) vl[l] = (double)x[hqlayout::low_neighbour(L, l, offDlo, offUlo, s_rank)];
+#pragma unroll
+        for (int k = 0; k < MAXH; ++k)
+            if (k < H) vh[k] = (double)x[bcast(r.seg, (uint32_t)k) + t];
         double U = 0.0, D = 0.0, mu_lo = 0.0;
-        // low units: neighbours in the small segments (T, q -+ 1)
-        {
-            double vl[HQ_MAXB];
 #pragma unroll
-            for (int l = 0; l < HQ_MAXB; ++l) {
-                if (l < b) {
-                    vl[l] = (double)x[hqlayout::low_neighbour(L, l, offDlo, offUlo, s_rank)];
-                }
-            }
-#pragma unroll
-            for (int l = 0; l < HQ_MAXB; ++l) {
-                if (l < b) {
-                    const double nl = nuc[l];
-                    if ((L >> l) & 1u) {
-                        const double c = STORED ? cs[(size_t)l * A.count + t] : tcT[l];
-                        U += c * vl[l];
-                        mu_lo += nl;
-                    } else {
-                        D += nl * vl[l];
-                    }
+        for (int l = 0; l < MAXB; ++l) {
+            if (l < b) {
+                const double nl = nuc[l];
+                if ((L >> l) & 1u) {
+                    const double c = STORED ? cs[(size_t)l * A.count + t] : unit_coef(P, r, l, L);
+                    U += c * vl[l];
+                    mu_lo += nl;
+                } else {
+                    D += nl * vl[l];
                 }
             }
         }
-        // high units: segment-aligned coalesced neighbours, HQ_HCHUNK loads in flight
 #pragma unroll
-        for (int k0 = 0; k0 < HQ_MAXH; k0 += HQ_HCHUNK) {
-            if (k0 < H) {
-                double vh[HQ_HCHUNK];
-#pragma unroll
-                for (int j = 0; j < HQ_HCHUNK; ++j)
-                    if (k0 + j < HQ_MAXH && k0 + j < H) vh[j] = (double)x[off[k0 + j] + t];
-#pragma unroll
-                for (int j = 0; j < HQ_HCHUNK; ++j) {
-                    const int k = k0 + j;
-                    if (k < HQ_MAXH && k < H) {
-                        if ((Tb >> k) & 1u)
-                            U += (STORED ? cs[(size_t)(b + k) * A.count + t] : tcT[b + k]) * vh[j];
-                        else
-                            D += nuc[b + k] * vh[j];
-                    }
-                }
-            }
-        }
-        // per-lane remainder of the dispatch walk: trie subtrees below a busy
-        // low unit whose path through high units is busy in T.  Indices are
-        // wave-uniform, so node reads are scalar loads.
-        if (!STORED) {
-            for (int l = 0; l < b; ++l) {
-                const uint32_t e0 = eo[l], e1 = eo[l + 1];
-                if (e0 == e1 || !__any((L >> l) & 1u)) continue;
-                for (uint32_t e = e0; e < e1; ++e) {
-                    const HQ_CONST uint32_t* rg =
-                        ro(reinterpret_cast<const uint32_t*>(P.ent_range)) + 2 * (size_t)__builtin_amdgcn_readfirstlane(e);
-                    uint32_t i = rg[0];
-                    const uint32_t end = rg[1];
-                    while (i < end) {
-                        const HQ_CONST TrieNode* nd = ro(P.nodes) + i;
-                        const uint32_t need = nd->need, su = nd->skip_unit;
-                        const bool hit = (m & need) == need;
-                        if (!__any(hit)) {
-                            i = __builtin_amdgcn_readfirstlane(su >> 5);
-                            continue;
-                        }
-                        if (hit) {
-                            const int u = (int)(su & 31u);
-                            const uint32_t idx =
-                                (u >= b) ? hqlayout::high_neighbour(ro(P.segoff), tiles, q, Tb, u - b, t)
-                                         : hqlayout::low_neighbour(L, u, offDlo, offUlo, s_rank);
-                            U += nd->rate * (double)x[idx];
-                        }
-                        i = __builtin_amdgcn_readfirstlane(i + 1);
-                    }
+        for (int k = 0; k < MAXH; ++k) {
+            if (k < H) {
+                if ((Tb >> k) & 1u) {
+                    const double c = STORED ? cs[(size_t)(b + k) * A.count + t] : unit_coef(P, r, b + k, L);
+                    U += c * vh[k];
+                } else {
+                    D += nuc[b + k] * vh[k];
                 }
             }
         }
@@ -347,10 +393,9 @@ __device__ __forceinline__ void segment_update(const SweepParams& P, const Layer
             }
         }
     }
-
 }
 
-template <typename T, int MODE, bool TRACK_DELTA, bool STORED>
+template <typename T, int MODE, bool TRACK_DELTA, bool STORED, int BF = 0, int HF = 0>
 __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
                                                       int inner_one) {
     __shared__ uint16_t s_rank[1 << HQ_MAXB];    // colex rank of a low pattern inside its class
@@ -369,7 +414,8 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     const WaveIter it = wave_iter(A.groups);
     for (uint32_t si = it.begin; si < it.end; si += it.step)
-        segment_update<T, MODE, TRACK_DELTA, STORED>(P, A, x, si, s_rank, s_unrank, s_qstart, ms, acc0, acc1, acc2);
+        segment_update<T, MODE, TRACK_DELTA, STORED, BF, HF>(P, A, x, si, s_rank, s_unrank, s_qstart, ms, acc0,
+                                                             acc1, acc2);
     block_partial3(acc0, acc1, acc2, P.partials);
 }
 
@@ -861,10 +907,40 @@ static uint32_t grid_for(uint32_t groups) {
     return g & ~7u;
 }
 
+// Fixed-shape kernels for the default tiles (b = 10 for N = 11..27, b = 12
+// for N = 28..30) in the two modes of every iteration; false if the shape
+// has none.
+template <typename T, int BF, int HF>
+static void launch_fixed(int mode, const SweepParams& P, const LayerArgs& A, T* x, int inner_one, hipStream_t s) {
+    dim3 grid(grid_for(A.groups)), block(HQ_WG);
+    if (mode == M_WRITE)
+        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+    else
+        hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+}
+
+template <typename T>
+static bool launch_layer_fixed(int mode, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
+                               hipStream_t s) {
+    if (mode != M_WRITE && mode != M_RESID) return false;
+#define HQ_FIXED(BV, HV)                                                   \
+    if (P.b == BV && P.H == HV) {                                          \
+        launch_fixed<T, BV, HV>(mode, P, A, x, inner_one, s);              \
+        return true;                                                       \
+    }
+    HQ_FIXED(10, 1) HQ_FIXED(10, 2) HQ_FIXED(10, 3) HQ_FIXED(10, 4) HQ_FIXED(10, 5) HQ_FIXED(10, 6)
+    HQ_FIXED(10, 7) HQ_FIXED(10, 8) HQ_FIXED(10, 9) HQ_FIXED(10, 10) HQ_FIXED(10, 11) HQ_FIXED(10, 12)
+    HQ_FIXED(10, 13) HQ_FIXED(10, 14) HQ_FIXED(10, 15) HQ_FIXED(10, 16) HQ_FIXED(10, 17)
+    HQ_FIXED(12, 16) HQ_FIXED(12, 17) HQ_FIXED(12, 18)
+#undef HQ_FIXED
+    return false;
+}
+
 template <typename T, bool STORED>
 static void launch_layer_s(int mode, bool track_delta, const SweepParams& P, const LayerArgs& A, T* x,
                            int inner_one, hipStream_t s) {
     dim3 grid(grid_for(A.groups)), block(HQ_WG);
+    if (!STORED && !track_delta && launch_layer_fixed<T>(mode, P, A, x, inner_one, s)) return;
     if (mode == M_PASS1)
         hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
     else if (mode == M_WRITE && track_delta)
