@@ -112,7 +112,7 @@ struct hq_ctx {
     double *d_nu = nullptr, *d_mu_lo = nullptr, *d_tcoef = nullptr, *d_scal = nullptr, *d_part = nullptr;
     double *d_scale64 = nullptr, *d_scale32 = nullptr, *d_rho = nullptr, *d_xu = nullptr, *d_given = nullptr;
     uint32_t *d_binom = nullptr, *d_layer_off = nullptr, *d_lo_qstart = nullptr, *d_prog_off = nullptr,
-             *d_orig_bit = nullptr, *d_seg_desc = nullptr, *d_segoff = nullptr;
+             *d_orig_bit = nullptr, *d_seg_desc = nullptr, *d_segoff = nullptr, *d_seg_prog = nullptr;
     ProgTerm* d_prog = nullptr;
     size_t prog_terms = 0;
     double* d_coefs = nullptr;
@@ -131,7 +131,7 @@ struct hq_ctx {
         void* ptrs[] = {x64,       x32,        d_nu,       d_mu_lo,    d_tcoef,     d_scal,     d_part,
                         d_scale64, d_scale32,  d_rho,      d_xu,       d_given,     d_binom,    d_layer_off,
                         d_lo_qstart, d_prog_off, d_prog, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
-                        d_counters, d_seg_desc, d_segoff,   d_coefs};
+                        d_counters, d_seg_desc, d_segoff,   d_coefs,     d_seg_prog};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         x64 = nullptr;
@@ -380,6 +380,7 @@ void setup_params(hq_ctx* c) {
     P.mu_lo = c->d_mu_lo;
     P.tcoef = c->d_tcoef;
     P.seg_desc = c->d_seg_desc;
+    P.seg_prog = reinterpret_cast<const uint2*>(c->d_seg_prog);
     P.segoff = c->d_segoff;
     P.prog_off = c->d_prog_off;
     P.prog = c->d_prog;
@@ -492,6 +493,13 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
             if ((L >> u) & 1u) mu_lo[L] += c->nu[u];
     const std::vector<uint32_t>& segoff = lay.segoff;
     const std::vector<uint32_t>& seg_desc = lay.seg_desc;
+    // per segment: where its tile's program starts and how many terms it has
+    std::vector<uint32_t> seg_prog(2 * seg_desc.size());
+    for (size_t i = 0; i < seg_desc.size(); ++i) {
+        const size_t T = seg_desc[i] >> 4;
+        seg_prog[2 * i] = prog_off[T * (N + 1)];
+        seg_prog[2 * i + 1] = prog_off[T * (N + 1) + N] - prog_off[T * (N + 1)];
+    }
     c->layers.resize(N + 1);
     size_t max_groups = 1;
     for (int n = 0; n <= N; ++n) {
@@ -568,6 +576,7 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->d_prog_off = dalloc<uint32_t>(prog_off.size());
         c->d_prog = dalloc<ProgTerm>(std::max<size_t>(prog.size(), 1));
         c->d_seg_desc = dalloc<uint32_t>(seg_desc.size());
+        c->d_seg_prog = dalloc<uint32_t>(seg_prog.size());
         c->d_segoff = dalloc<uint32_t>(segoff.size());
         c->d_coefs = dalloc<double>(coef_total);
         c->d_orig_bit = dalloc<uint32_t>(N);
@@ -587,6 +596,7 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         h2d(c->d_prog_off, prog_off, s);
         if (!prog.empty()) h2d(c->d_prog, prog, s);
         h2d(c->d_seg_desc, seg_desc, s);
+        h2d(c->d_seg_prog, seg_prog, s);
         h2d(c->d_segoff, segoff, s);
         h2d(c->d_orig_bit, orig_bit, s);
         h2d(c->d_lo_unrank, lo_unrank, s);

@@ -69,6 +69,7 @@ struct SweepParams {
     const uint32_t* segoff;      // [(b+1) * 2^H] absolute start of segment (T, q)
     const uint32_t* prog_off;    // [2^H * (N+1)] per tile: first program term of unit u, and the end
     const ProgTerm* prog;        // per-tile dispatch programs, grouped by unit
+    const uint2* seg_prog;       // per seg_desc entry: (first program term, term count) of its tile
     const TrieNode* nodes;
     const double* coefs;         // stored coefficients of the top layers (unit-major per layer)
     const double* scale;         // [N+1] storage scale of each layer (x = scale * p)

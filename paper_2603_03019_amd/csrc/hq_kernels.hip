@@ -219,24 +219,44 @@ __device__ __forceinline__ double bcast(double v, uint32_t i) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Up to HQ_PROG_REG program terms of a tile are held in registers, the rest
-// are read as scalar loads.
-#define HQ_PROG_REG 128
+// The first 64 program terms of a tile are held in registers (lane i holds
+// term i), the rest are read as scalar loads.
+#define HQ_PROG_REG 64
 
-struct SegRecord {
-    uint32_t seg;   // lane k < H: start of segment (T xor e_k, q); lane H, H+1, H+2: (T, q-1), (T, q+1), (T, q)
-    uint32_t po;    // lane u <= N: prog_off[T][u]
-    double tc;      // lane u < N: tcoef[T][u]
-    uint32_t pm0, pm1;  // program terms 0..63 and 64..127 of the tile: masks
-    double pr0, pr1;    //   and rates
+// Wave-uniform part of a segment's record: descriptor and the position of
+// its tile's program.  Fetched two segments ahead.
+struct SegScal {
+    uint32_t desc;    // (T << 4) | q
+    uint32_t pstart;  // first program term of the tile
+    uint32_t pcount;  // number of program terms
 };
 
-__device__ __forceinline__ SegRecord load_record(const SweepParams& P, int b, int H, int q, uint32_t Tb,
-                                                 bool stored) {
+// Lane-parallel part, fetched one segment ahead so that its loads overlap
+// the previous segment's work.
+struct SegVec {
+    uint32_t seg;  // lane k < H: start of segment (T xor e_k, q); lanes H, H+1, H+2: (T, q-1), (T, q+1), (T, q)
+    uint32_t po;   // lane u <= N: prog_off[T][u]
+    double tc;     // lane u < N: tcoef[T][u]
+    uint32_t pm;   // lane i: mask of program term i
+    double pr;     //         and its rate
+};
+
+__device__ __forceinline__ SegScal fetch_scal(const SweepParams& P, const LayerArgs& A, uint32_t si) {
+    SegScal r;
+    r.desc = ro(P.seg_desc)[A.desc_base + si];
+    const HQ_CONST uint32_t* sp = ro(reinterpret_cast<const uint32_t*>(P.seg_prog)) + 2 * (size_t)(A.desc_base + si);
+    r.pstart = sp[0];
+    r.pcount = sp[1];
+    return r;
+}
+
+__device__ __forceinline__ SegVec fetch_vec(const SweepParams& P, int b, int H, const SegScal& sc, bool stored) {
     const int lane = threadIdx.x & 63;
     const int N = P.N;
     const uint32_t tiles = 1u << H;
-    SegRecord r;
+    const int q = (int)(sc.desc & 15u);
+    const uint32_t Tb = sc.desc >> 4;
+    SegVec r;
     r.seg = 0u;
     if (lane < H)
         r.seg = P.segoff[hqlayout::seg_index(q, Tb ^ (1u << lane), tiles)];
@@ -248,42 +268,33 @@ __device__ __forceinline__ SegRecord load_record(const SweepParams& P, int b, in
         r.seg = P.segoff[hqlayout::seg_index(q, Tb, tiles)];
     r.po = 0u;
     r.tc = 0.0;
-    r.pm0 = r.pm1 = 0u;
-    r.pr0 = r.pr1 = 0.0;
+    r.pm = 0u;
+    r.pr = 0.0;
     if (stored) return r;
     if (lane <= N) r.po = P.prog_off[(size_t)Tb * (N + 1) + lane];
     if (lane < N) r.tc = P.tcoef[(size_t)Tb * N + lane];
-    const uint32_t p0 = bcast(r.po, 0u), nt = bcast(r.po, (uint32_t)N) - p0;
-    if ((uint32_t)lane < nt) {
-        const ProgTerm t = P.prog[p0 + lane];
-        r.pm0 = t.mask;
-        r.pr0 = t.rate;
-    }
-    if (nt > 64u && (uint32_t)lane + 64u < nt) {
-        const ProgTerm t = P.prog[p0 + 64u + lane];
-        r.pm1 = t.mask;
-        r.pr1 = t.rate;
+    if ((uint32_t)lane < sc.pcount) {
+        const ProgTerm t = P.prog[sc.pstart + lane];
+        r.pm = t.mask;
+        r.pr = t.rate;
     }
     return r;
 }
 
 // Arrival coefficient of busy unit u for the lane's low pattern L: the
 // tile-uniform part plus the unit's program terms whose mask lies in L.
-__device__ __forceinline__ double unit_coef(const SweepParams& P, const SegRecord& r, int u, uint32_t L) {
+__device__ __forceinline__ double unit_coef(const SweepParams& P, const SegScal& sc, const SegVec& r, int u,
+                                            uint32_t L) {
     double c = bcast(r.tc, (uint32_t)u);
-    const uint32_t p0 = bcast(r.po, 0u);
-    const uint32_t i0 = bcast(r.po, (uint32_t)u) - p0, i1 = bcast(r.po, (uint32_t)u + 1u) - p0;
+    const uint32_t i0 = bcast(r.po, (uint32_t)u) - sc.pstart, i1 = bcast(r.po, (uint32_t)u + 1u) - sc.pstart;
     for (uint32_t i = i0; i < i1; ++i) {
         uint32_t mk;
         double rt;
-        if (i < 64u) {
-            mk = bcast(r.pm0, i);
-            rt = bcast(r.pr0, i);
-        } else if (i < HQ_PROG_REG) {
-            mk = bcast(r.pm1, i - 64u);
-            rt = bcast(r.pr1, i - 64u);
+        if (i < HQ_PROG_REG) {
+            mk = bcast(r.pm, i);
+            rt = bcast(r.pr, i);
         } else {
-            const HQ_CONST ProgTerm* t = ro(P.prog) + p0 + i;
+            const HQ_CONST ProgTerm* t = ro(P.prog) + sc.pstart + i;
             mk = t->mask;
             rt = t->rate;
         }
@@ -292,20 +303,20 @@ __device__ __forceinline__ double unit_coef(const SweepParams& P, const SegRecor
     return c;
 }
 
-// One wave updates (or, for M_RESID / M_PASS1, evaluates) the states of
-// segment `si` of layer A.n; accumulates the layer sums in acc0..acc2.
-// Every state reads its N neighbours once, all loads issued together; the
-// arrival coefficient of busy unit u is tcoef[T][u] plus the lane's terms
-// of the tile program of u (or, with STORED, the stored a(m, u)).
-// BF, HF: the tile shape (low bits b, high bits H) fixed at compile time,
-// or 0 to take it from P.  With a fixed shape the unrolled per-unit code
-// needs no run-time guards, which keeps the register budget at 4 waves per
-// SIMD.
+// One wave updates (or, for M_RESID / M_PASS1, evaluates) the states of one
+// segment of layer A.n from its fetched record; accumulates the layer sums
+// in acc0..acc2.  Every state reads its N neighbours once, all loads issued
+// together; the arrival coefficient of busy unit u is tcoef[T][u] plus the
+// lane's terms of the tile program of u (or, with STORED, the stored
+// a(m, u)).  BF, HF: the tile shape (low bits b, high bits H) fixed at
+// compile time, or 0 to take it from P.  With a fixed shape the unrolled
+// per-unit code needs no run-time guards, which keeps the register budget
+// at 4 waves per SIMD.
 template <typename T, int MODE, bool TRACK_DELTA, bool STORED, int BF = 0, int HF = 0>
-__device__ __forceinline__ void segment_update(const SweepParams& P, const LayerArgs& A, T* __restrict__ x,
-                                               uint32_t si, const uint16_t* s_rank, const uint16_t* s_unrank,
-                                               const uint32_t* s_qstart, const ModeScalars& ms, double& acc0,
-                                               double& acc1, double& acc2) {
+__device__ __forceinline__ void segment_compute(const SweepParams& P, const LayerArgs& A, T* __restrict__ x,
+                                                const SegScal& sc, const SegVec& r, const uint16_t* s_rank,
+                                                const uint16_t* s_unrank, const uint32_t* s_qstart,
+                                                const ModeScalars& ms, double& acc0, double& acc1, double& acc2) {
     constexpr int MAXB = BF ? BF : HQ_MAXB, MAXH = HF ? HF : HQ_MAXH;
     const int lane = threadIdx.x & 63;
     const int n = A.n, N = P.N;
@@ -314,10 +325,8 @@ __device__ __forceinline__ void segment_update(const SweepParams& P, const Layer
     const HQ_CONST double* nuc = ro(P.nu);
     const double alpha = ms.alpha, beta = ms.beta, pdn = ms.pdn, pself = ms.pself, pup = ms.pup;
     const double is_dn = ms.is_dn, is_up = ms.is_up, s_self = ms.s_self, is_self = ms.is_self;
-    const uint32_t d = ro(P.seg_desc)[A.desc_base + si];
-    const int q = (int)(d & 15u);
-    const uint32_t Tb = d >> 4;
-    const SegRecord r = load_record(P, b, H, q, Tb, STORED);
+    const int q = (int)(sc.desc & 15u);
+    const uint32_t Tb = sc.desc >> 4;
     const uint32_t offDlo = bcast(r.seg, (uint32_t)H), offUlo = bcast(r.seg, (uint32_t)H + 1u);
     const uint32_t offSelf = bcast(r.seg, (uint32_t)H + 2u);
     double mu_hi = 0.0;
@@ -346,7 +355,7 @@ __device__ __forceinline__ void segment_update(const SweepParams& P, const Layer
             if (l < b) {
                 const double nl = nuc[l];
                 if ((L >> l) & 1u) {
-                    const double c = STORED ? cs[(size_t)l * A.count + t] : unit_coef(P, r, l, L);
+                    const double c = STORED ? cs[(size_t)l * A.count + t] : unit_coef(P, sc, r, l, L);
                     U += c * vl[l];
                     mu_lo += nl;
                 } else {
@@ -358,7 +367,7 @@ __device__ __forceinline__ void segment_update(const SweepParams& P, const Layer
         for (int k = 0; k < MAXH; ++k) {
             if (k < H) {
                 if ((Tb >> k) & 1u) {
-                    const double c = STORED ? cs[(size_t)(b + k) * A.count + t] : unit_coef(P, r, b + k, L);
+                    const double c = STORED ? cs[(size_t)(b + k) * A.count + t] : unit_coef(P, sc, r, b + k, L);
                     U += c * vh[k];
                 } else {
                     D += nuc[b + k] * vh[k];
@@ -395,6 +404,17 @@ __device__ __forceinline__ void segment_update(const SweepParams& P, const Layer
     }
 }
 
+// Fetch and process one segment (no look-ahead; used by the batch kernel).
+template <typename T, int MODE, bool TRACK_DELTA, bool STORED>
+__device__ __forceinline__ void segment_update(const SweepParams& P, const LayerArgs& A, T* __restrict__ x,
+                                               uint32_t si, const uint16_t* s_rank, const uint16_t* s_unrank,
+                                               const uint32_t* s_qstart, const ModeScalars& ms, double& acc0,
+                                               double& acc1, double& acc2) {
+    const SegScal sc = fetch_scal(P, A, si);
+    const SegVec r = fetch_vec(P, P.b, P.H, sc, STORED);
+    segment_compute<T, MODE, TRACK_DELTA, STORED>(P, A, x, sc, r, s_rank, s_unrank, s_qstart, ms, acc0, acc1, acc2);
+}
+
 template <typename T, int MODE, bool TRACK_DELTA, bool STORED, int BF = 0, int HF = 0>
 __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
                                                       int inner_one) {
@@ -403,7 +423,7 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
     __shared__ uint32_t s_qstart[HQ_MAXB + 2];
 
     const int tid = threadIdx.x;
-    const int b = P.b;
+    const int b = BF ? BF : P.b, H = HF ? HF : P.H;
     for (int i = tid; i < (1 << b); i += HQ_WG) {
         s_rank[i] = P.lo_rank[i];
         s_unrank[i] = P.lo_unrank[i];
@@ -412,10 +432,28 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
     __syncthreads();
     const ModeScalars ms = mode_scalars<MODE>(P, A.n, inner_one, P.sc.lam, P.sc.mu, P.sc.alpha, P.sc.pn);
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    // Software pipeline over this wave's segments: the scalar record of
+    // segment i+2 and the lane-parallel record of segment i+1 are in flight
+    // while segment i is processed.
     const WaveIter it = wave_iter(A.groups);
-    for (uint32_t si = it.begin; si < it.end; si += it.step)
-        segment_update<T, MODE, TRACK_DELTA, STORED, BF, HF>(P, A, x, si, s_rank, s_unrank, s_qstart, ms, acc0,
-                                                             acc1, acc2);
+    SegScal s0{}, s1{};
+    SegVec v0{};
+    if (it.begin < it.end) {
+        s0 = fetch_scal(P, A, it.begin);
+        v0 = fetch_vec(P, b, H, s0, STORED);
+    }
+    if (it.begin + it.step < it.end) s1 = fetch_scal(P, A, it.begin + it.step);
+    for (uint32_t si = it.begin; si < it.end; si += it.step) {
+        SegVec v1{};
+        SegScal s2{};
+        if (si + it.step < it.end) v1 = fetch_vec(P, b, H, s1, STORED);
+        if (si + 2 * it.step < it.end) s2 = fetch_scal(P, A, si + 2 * it.step);
+        segment_compute<T, MODE, TRACK_DELTA, STORED, BF, HF>(P, A, x, s0, v0, s_rank, s_unrank, s_qstart, ms, acc0,
+                                                              acc1, acc2);
+        s0 = s1;
+        v0 = v1;
+        s1 = s2;
+    }
     block_partial3(acc0, acc1, acc2, P.partials);
 }
 
@@ -907,30 +945,33 @@ static uint32_t grid_for(uint32_t groups) {
     return g & ~7u;
 }
 
-// Fixed-shape kernels for the default tiles (b = 10 for N = 11..27, b = 12
-// for N = 28..30) in the two modes of every iteration; false if the shape
-// has none.
+// Fixed-shape kernels for the default tiles of the larger instances (b = 10
+// for N = 16..27, b = 12 for N = 28..30): the sweep (with computed or
+// stored coefficients) and the residual.  Other shapes and modes use the
+// run-time-shaped kernels.
 template <typename T, int BF, int HF>
-static void launch_fixed(int mode, const SweepParams& P, const LayerArgs& A, T* x, int inner_one, hipStream_t s) {
+static void launch_fixed(int mode, bool stored, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
+                         hipStream_t s) {
     dim3 grid(grid_for(A.groups)), block(HQ_WG);
-    if (mode == M_WRITE)
+    if (mode == M_WRITE && stored)
+        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, true, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+    else if (mode == M_WRITE)
         hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
     else
         hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
 }
 
 template <typename T>
-static bool launch_layer_fixed(int mode, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
-                               hipStream_t s) {
-    if (mode != M_WRITE && mode != M_RESID) return false;
+static bool launch_layer_fixed(int mode, bool stored, const SweepParams& P, const LayerArgs& A, T* x,
+                               int inner_one, hipStream_t s) {
+    if (mode != M_WRITE && (mode != M_RESID || stored)) return false;
 #define HQ_FIXED(BV, HV)                                                   \
     if (P.b == BV && P.H == HV) {                                          \
-        launch_fixed<T, BV, HV>(mode, P, A, x, inner_one, s);              \
+        launch_fixed<T, BV, HV>(mode, stored, P, A, x, inner_one, s);      \
         return true;                                                       \
     }
-    HQ_FIXED(10, 1) HQ_FIXED(10, 2) HQ_FIXED(10, 3) HQ_FIXED(10, 4) HQ_FIXED(10, 5) HQ_FIXED(10, 6)
-    HQ_FIXED(10, 7) HQ_FIXED(10, 8) HQ_FIXED(10, 9) HQ_FIXED(10, 10) HQ_FIXED(10, 11) HQ_FIXED(10, 12)
-    HQ_FIXED(10, 13) HQ_FIXED(10, 14) HQ_FIXED(10, 15) HQ_FIXED(10, 16) HQ_FIXED(10, 17)
+    HQ_FIXED(10, 6) HQ_FIXED(10, 7) HQ_FIXED(10, 8) HQ_FIXED(10, 9) HQ_FIXED(10, 10) HQ_FIXED(10, 11)
+    HQ_FIXED(10, 12) HQ_FIXED(10, 13) HQ_FIXED(10, 14) HQ_FIXED(10, 15) HQ_FIXED(10, 16) HQ_FIXED(10, 17)
     HQ_FIXED(12, 16) HQ_FIXED(12, 17) HQ_FIXED(12, 18)
 #undef HQ_FIXED
     return false;
@@ -940,7 +981,7 @@ template <typename T, bool STORED>
 static void launch_layer_s(int mode, bool track_delta, const SweepParams& P, const LayerArgs& A, T* x,
                            int inner_one, hipStream_t s) {
     dim3 grid(grid_for(A.groups)), block(HQ_WG);
-    if (!STORED && !track_delta && launch_layer_fixed<T>(mode, P, A, x, inner_one, s)) return;
+    if (!track_delta && launch_layer_fixed<T>(mode, STORED, P, A, x, inner_one, s)) return;
     if (mode == M_PASS1)
         hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
     else if (mode == M_WRITE && track_delta)
