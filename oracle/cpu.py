@@ -63,6 +63,8 @@ def lib():
         L.orc_marginals.restype = None
         L.orc_marginals.argtypes = [ctypes.c_int, d, d, d]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_birth_death.restype = ctypes.c_int
+        L.orc_birth_death.argtypes = [ctypes.c_int, d, d, ctypes.c_double, ctypes.c_double, ctypes.c_int, d, d, d]
         L.orc_balance_terms.restype = None
         L.orc_balance_terms.argtypes = [ctypes.c_int, ctypes.c_int, d, d, i32, ctypes.c_longlong, u32, d, d, d]
         _lib = L
@@ -219,3 +221,31 @@ def balance_terms(inst, states: np.ndarray, P: np.ndarray):
     lib().orc_balance_terms(inst.N, inst.J, _dp(lam), _dp(nu), _ip(pref), len(st), _up(st),
                             _dp(np.ascontiguousarray(P, dtype=np.float64)), _dp(out), _dp(of))
     return out, of
+
+
+def birth_death(res: OracleResult, inst, C: int):
+    """Marginal of the system with a waiting room of C calls (C < 0:
+    unlimited), Proposition 2, from the lambda(n), mu(n) of a loss-system
+    solve.  Returns (p[N+1], tail[C] or None, summary[4]) with summary =
+    (P(all busy), P(wait), mean waiting, P(lost))."""
+    N = inst.N
+    p = np.zeros(N + 1)
+    tail = np.zeros(C) if C > 0 else None
+    summ = np.zeros(4)
+    rc = lib().orc_birth_death(N, _dp(np.ascontiguousarray(res.lam_n)), _dp(np.ascontiguousarray(res.mu_n)),
+                               float(np.sum(inst.lam)), float(np.sum(inst.nu)), int(C), _dp(p), _dp(tail),
+                               _dp(summ))
+    if rc != 0:
+        raise ValueError("unlimited waiting room needs Lambda < sum of service rates")
+    return p, tail, summ
+
+
+def buffered_state(res: OracleResult, inst, C: int):
+    """P over the 2^N unit states of the buffered system: the loss-system
+    layers p_n(m) times the buffered p(n) (Proposition 2)."""
+    p, tail, summ = birth_death(res, inst, C)
+    scale = np.zeros(inst.N + 1)
+    for n in range(inst.N + 1):
+        scale[n] = p[n] / res.p_n[n] if res.p_n[n] > 0 else 0.0
+    pop = np.array([bin(m).count("1") for m in range(1 << inst.N)])
+    return res.P * scale[pop], tail, summ

@@ -131,3 +131,55 @@ def ordered_hunting_rho(pref_row, N: int, a: float) -> np.ndarray:
     for h in range(1, N + 1):
         rho[int(pref_row[h - 1])] = a * (erlang_b(h - 1, a) - erlang_b(h, a))
     return rho
+
+
+def buffered_dense_solve(inst, C: int):
+    """Stationary law of the chain with a waiting room of C calls, built
+    from first principles (not from the reformulation): unit states
+    0..2^N-1 as in generator_matrix, plus waiting states S-1+c, c = 1..C
+    (all units busy, c calls waiting, first come first served).  From the
+    full state an arrival moves to c = 1; from c an arrival moves to c + 1
+    (lost when c = C); any completion at a waiting state hands the next call
+    to the freed unit, so c drops by one.  Returns (P over unit states,
+    P~ over waiting states)."""
+    N = inst.N
+    S = 1 << N
+    full = S - 1
+    lam_tot = float(np.sum(inst.lam))
+    nu_tot = float(np.sum(inst.nu))
+    T = S + C
+    Q = np.zeros((T, T))
+    Q[:S, :S] = generator_matrix(inst)
+    # generator_matrix has no arrivals out of the full state; add them
+    if C > 0:
+        Q[full, S] += lam_tot
+        Q[full, full] -= lam_tot
+        for c in range(1, C + 1):
+            i = S + c - 1
+            if c < C:
+                Q[i, i + 1] += lam_tot
+            below = full if c == 1 else i - 1
+            Q[i, below] += nu_tot
+            Q[i, i] -= Q[i].sum() - Q[i, i]
+    A = Q.T.copy()
+    A[-1, :] = 1.0
+    b = np.zeros(T)
+    b[-1] = 1.0
+    x = np.linalg.solve(A, b)
+    return x[:S], x[S:]
+
+
+def buffered_erlang_marginal(N: int, a: float, C: int) -> np.ndarray:
+    """M/M/N/N+C law of the number in system, n = 0..N+C (homogeneous unit
+    rates, a = Lambda / nu): a^n / n! up to N, then a^N / N! (a / N)^(n-N)."""
+    w = [1.0]
+    for n in range(1, N + C + 1):
+        w.append(w[-1] * a / min(n, N))
+    w = np.array(w)
+    return w / w.sum()
+
+
+def erlang_c(N: int, a: float) -> float:
+    """Probability that an arrival waits in M/M/N with unlimited room, a < N."""
+    B = erlang_b(N, a)
+    return N * B / (N - a * (1.0 - B))

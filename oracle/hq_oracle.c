@@ -546,3 +546,67 @@ void orc_balance_terms(int N, int J, const double* lam, const double* nu, const 
         free(a);
     }
 }
+
+/*
+ * Birth-death marginal of the buffered system, Proposition 2 and the remark
+ * after it (Section 2.2).  With a waiting room of C calls the conditional
+ * layer probabilities p_n are those of the loss system; only the marginal
+ * changes: lambda(N) = Lambda (an arrival at the full state waits),
+ * lambda(n) = Lambda for N < n < N + C, lambda(N + C) = 0, and
+ * mu(n) = sum_i nu_i for n > N.  G(n) is the running product of
+ * lambda(n-1) / mu(n); p(n) = G(n) p(0) with p(0) = 1 / sum_n G(n).
+ *   lamn, mun: lambda(n), mu(n) for n = 0..N of a loss-system solve
+ *              (lamn[N] is not used);
+ *   C: waiting room (C >= 0); C < 0 means unlimited, which needs
+ *      Lambda < sum_i nu_i (the geometric series of the remark);
+ *   p: [N + 1] out, p(n) for n = 0..N (all units busy and nobody waiting
+ *      for n = N);
+ *   tail: [C] out (nullable; finite C only), P~{c} = p(N + c);
+ *   summary: [4] out: P(all units busy), P(at least one call waits),
+ *      mean number waiting, P(an arrival is lost).
+ * Returns 0, or -1 for an unlimited room that is not stable.
+ */
+int orc_birth_death(int N, const double* lamn, const double* mun, double Lam, double sum_nu, int C,
+                    double* p, double* tail, double* summary) {
+    const double rho = Lam / sum_nu;
+    if (C < 0 && !(rho < 1.0)) return -1;
+    /* G(n) for n <= N by the product of the ratios */
+    double* g = (double*)malloc(sizeof(double) * (N + 1));
+    g[0] = 1.0;
+    for (int n = 1; n <= N; ++n) g[n] = g[n - 1] * lamn[n - 1] / mun[n];
+    double Z = 0.0;
+    for (int n = 0; n <= N; ++n) Z += g[n];
+    /* G(N + c) = G(N) rho^c, c = 1..C, summed term by term (finite) or as
+     * the geometric series rho / (1 - rho) (unlimited) */
+    double wait = 0.0, wait_mean = 0.0;
+    if (C > 0) {
+        double r = 1.0;
+        for (int c = 1; c <= C; ++c) {
+            r *= rho;
+            wait += g[N] * r;
+            wait_mean += c * g[N] * r;
+        }
+    } else if (C < 0) {
+        wait = g[N] * rho / (1.0 - rho);
+        wait_mean = g[N] * rho / ((1.0 - rho) * (1.0 - rho));
+    }
+    Z += wait;
+    for (int n = 0; n <= N; ++n) p[n] = g[n] / Z;
+    if (tail && C > 0) {
+        double r = 1.0;
+        for (int c = 1; c <= C; ++c) {
+            r *= rho;
+            tail[c - 1] = g[N] * r / Z;
+        }
+    }
+    summary[0] = p[N] + wait / Z;
+    summary[1] = wait / Z;
+    summary[2] = wait_mean / Z;
+    /* arrivals see time averages: lost at the full state (C = 0) or with
+     * the waiting room full (C > 0); never with unlimited room */
+    if (C == 0) summary[3] = p[N];
+    else if (C > 0) summary[3] = g[N] * pow(rho, C) / Z;
+    else summary[3] = 0.0;
+    free(g);
+    return 0;
+}

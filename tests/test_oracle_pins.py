@@ -411,3 +411,52 @@ def test_balance_terms_match_generator():
     terms, out = cpu.balance_terms(inst, states, P)
     np.testing.assert_allclose(terms, P @ Q, rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(out, -np.diag(Q) * P, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Waiting room (Proposition 2 and the remark after it)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N,C,idx", [(5, 1, 0), (6, 3, 1), (7, 2, 2)])
+def test_buffered_marginal_matches_full_chain(N, C, idx):
+    # the reformulation (loss-system layers + birth-death tail) against a
+    # dense solve of the whole chain built per source, waiting states included
+    inst = config_instance(1, idx, N=N, J=12)
+    res = cpu.solve(inst, tol=1e-14)
+    P, tail, summ = cpu.buffered_state(res, inst, C)
+    Pd, tail_d = exact.buffered_dense_solve(inst, C)
+    np.testing.assert_allclose(P, Pd, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(tail, tail_d, rtol=1e-9)
+    assert P.sum() + tail.sum() == pytest.approx(1.0, abs=1e-12)
+    assert summ[1] == pytest.approx(tail_d.sum(), rel=1e-9)
+    assert summ[3] == pytest.approx(tail_d[-1], rel=1e-9)  # arrivals find the room full
+    assert summ[2] == pytest.approx(np.dot(np.arange(1, C + 1), tail_d), rel=1e-9)
+
+
+def test_buffered_homogeneous_closed_form():
+    # equal unit rates: the number in system is M/M/N/N+C whatever the lists
+    N, C = 6, 4
+    inst = config_instance(1, 3, N=N, J=20, homogeneous=True)
+    a = float(np.sum(inst.lam)) / float(inst.nu[0])
+    res = cpu.solve(inst, tol=1e-14)
+    p, tail, summ = cpu.birth_death(res, inst, C)
+    want = exact.buffered_erlang_marginal(N, a, C)
+    np.testing.assert_allclose(np.r_[p, tail], want, rtol=1e-11)
+
+
+def test_unlimited_room_erlang_c_and_limit():
+    # unlimited room: P(wait) is Erlang C for equal rates, and a long finite
+    # room converges to the geometric tail of the remark
+    N = 6
+    inst = config_instance(1, 4, N=N, J=20, homogeneous=True)
+    inst = inst.__class__(**{**inst.__dict__, "lam": inst.lam * (4.5 / float(np.sum(inst.lam)))})
+    a = 4.5 / float(inst.nu[0])
+    res = cpu.solve(inst, tol=1e-14)
+    p, _, summ = cpu.birth_death(res, inst, -1)
+    assert summ[1] + p[N] == pytest.approx(exact.erlang_c(N, a), rel=1e-11)
+    assert summ[3] == 0.0
+    p2, tail2, summ2 = cpu.birth_death(res, inst, 400)
+    np.testing.assert_allclose(p2, p, rtol=1e-12)
+    assert summ2[2] == pytest.approx(summ[2], rel=1e-10)
+    with pytest.raises(ValueError):
+        over = inst.__class__(**{**inst.__dict__, "lam": inst.lam * 2.0})
+        cpu.birth_death(cpu.solve(over, tol=1e-10), over, -1)
