@@ -30,6 +30,8 @@
 extern "C" {
 #endif
 
+#define HQ_BUFFER_UNLIMITED (-1)
+#define HQ_BUFFER_MAX 65536 /* largest finite waiting room */
 #define HQ_MAX_N 30 /* 2^30 states; colex ranks and layer offsets fit in uint32 */
 
 typedef struct hq_ctx hq_ctx; /* opaque; owns its host and device memory */
@@ -93,6 +95,10 @@ typedef struct {
     const double* init_state; /* [2^N] conditional probabilities for HQ_INIT_STATE (copied) */
     void* stream;             /* hipStream_t to run on (e.g. torch's current stream); NULL = own stream */
     const hq_mlp* mlp;        /* network for HQ_INIT_LEARNED (evaluated during hq_create) */
+    int buffer;               /* waiting room for calls that find every unit busy (Section 2.2,
+                                 Proposition 2): 0 = none (loss system), 0 < C <= HQ_BUFFER_MAX =
+                                 at most C waiting calls, HQ_BUFFER_UNLIMITED = no limit (needs
+                                 Lambda < sum mu_i) */
 } hq_options;
 
 typedef struct {
@@ -110,8 +116,8 @@ typedef struct {
                                     the uniform start was used (no warm start, or fallback) */
 } hq_info;
 
-/* Fill *opts with the defaults (FP64, closed inner form, uniform init,
- * residual stop, adaptive checks). */
+/* Fill *opts with the defaults (FP64, one inner update per layer, uniform
+ * init, residual stop, adaptive checks, no waiting room). */
 void hq_default_options(hq_options* opts);
 
 /*
@@ -143,10 +149,29 @@ hq_status hq_solve(hq_ctx* ctx, double tol, hq_info* info);
 /*
  * Marginals of the last iterate (Proposition 1: P(m) = p(|m|) p_|m|(m)):
  *   rho_u [N]   (nullable) busy probability of each unit, sum_{m containing u} P(m)
- *   p_n   [N+1] (nullable) number-busy distribution p(n) of (10)
+ *   p_n   [N+1] (nullable) number-busy distribution p(n) of (10); with a
+ *               waiting room p_n[N] includes the states with calls waiting
  * P is renormalised to sum 1 first.  HQ_ERR_STATE before any solve.
  */
 hq_status hq_marginals(const hq_ctx* ctx, double* rho_u, double* p_n);
+
+/*
+ * Waiting-room measures of the last iterate (Section 2.2, Proposition 2 and
+ * the remark after it).  A waiting room changes only the birth-death
+ * marginal: the layers p_n(m) are those of the loss system, and the states
+ * with every unit busy and c calls waiting have P~{c} = p(N) rho^c with
+ * rho = Lambda / sum mu_i.
+ *   summary [4] (nullable) P(every unit busy, waiting calls included),
+ *               P(at least one call waits), mean number of waiting calls,
+ *               P(an arriving call is lost) (P(full) without a room, the
+ *               room-full probability with C > 0, 0 when unlimited)
+ *   tail    [len] (nullable) P~{c} for c = 1..len; entries beyond C are 0
+ * With buffer = 0 every waiting quantity is 0.  hq_state and hq_marginals
+ * already include the room: P over the 2^N unit states sums to
+ * 1 - P(at least one call waits), and rho_u and p_n(N) count the waiting
+ * states as all units busy.  HQ_ERR_STATE before any solve.
+ */
+hq_status hq_queue(const hq_ctx* ctx, double* summary, double* tail, int len);
 
 /* Export P [2^N] (bitmask order, renormalised to sum 1) to host memory.
  * HQ_ERR_STATE before any solve. */

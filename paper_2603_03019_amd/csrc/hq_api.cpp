@@ -370,7 +370,10 @@ void setup_params(hq_ctx* c) {
     P.N = c->N;
     P.b = c->b;
     P.H = c->H;
+    P.buffer = c->opts.buffer;
     P.Lam = c->Lam;
+    P.sum_nu = 0.0;
+    for (int u = 0; u < c->N; ++u) P.sum_nu += c->nu[u];
     P.nu = c->d_nu;
     P.binom = c->d_binom;
     P.layer_off = c->d_layer_off;
@@ -420,6 +423,14 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     if (o.stop != HQ_STOP_RESIDUAL && o.stop != HQ_STOP_DELTA) return fail(HQ_ERR_INVALID_ARG, "unknown stop rule");
     if (o.init == HQ_INIT_PRODUCT && !o.init_rho) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_PRODUCT needs init_rho");
     if (o.init == HQ_INIT_STATE && !o.init_state) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_STATE needs init_state");
+    if (o.buffer < HQ_BUFFER_UNLIMITED || o.buffer > HQ_BUFFER_MAX)
+        return fail(HQ_ERR_INVALID_ARG, "buffer must be in [0, HQ_BUFFER_MAX] or HQ_BUFFER_UNLIMITED");
+    if (o.buffer == HQ_BUFFER_UNLIMITED) {
+        double L = 0.0, M = 0.0;
+        for (int j = 0; j < J; ++j) L += lam[j];
+        for (int u = 0; u < N; ++u) M += mu[u];
+        if (!(L < M)) return fail(HQ_ERR_INVALID_ARG, "an unlimited waiting room needs sum lambda_j < sum mu_i");
+    }
     if (o.tile_bits > 0 && (o.tile_bits < 1 || o.tile_bits > HQ_MAXB))
         return fail(HQ_ERR_INVALID_ARG, "tile_bits must be in [1, 12]");
     if (o.init == HQ_INIT_PRODUCT)
@@ -1089,7 +1100,7 @@ void hq_default_options(hq_options* o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
     o->precision = HQ_FP64;
-    o->inner = HQ_INNER_CLOSED;
+    o->inner = HQ_INNER_ONE;
     o->init = HQ_INIT_UNIFORM;
     o->stop = HQ_STOP_RESIDUAL;
     o->max_iters = 100000;
@@ -1260,18 +1271,60 @@ hq_status hq_marginals(const hq_ctx* cc, double* rho_u, double* p_n) {
         HQ_HIP(hipMemcpyAsync(rho.data(), c->d_rho, 32 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HQ_HIP(hipMemcpyAsync(scal.data(), c->d_scal, scal.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HQ_HIP(hipStreamSynchronize(c->stream));
+        const int L = N + 1;
+        const double mass = scal[7 * L + 1];
+        const double wait = scal[7 * L + 3] / mass;  // states with calls waiting: every unit busy
         if (rho_u)
-            for (int u = 0; u < N; ++u) rho_u[c->orig[u]] = rho[u];
+            for (int u = 0; u < N; ++u) rho_u[c->orig[u]] = rho[u] + wait;
         if (p_n) {
-            const int L = N + 1;
-            const double mass = scal[7 * L + 1];
             for (int n = 0; n <= N; ++n) {
                 const double layer_sum = (n == N) ? 1.0 : scal[n] / c->Lam;
                 p_n[n] = scal[3 * L + n] * layer_sum / mass;
             }
+            p_n[N] += wait;
         }
     } catch (const HipError& e) {
         return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    return HQ_OK;
+}
+
+hq_status hq_queue(const hq_ctx* cc, double* summary, double* tail, int len) {
+    if (!cc) return fail(HQ_ERR_INVALID_ARG, "ctx is NULL");
+    if (tail && len < 0) return fail(HQ_ERR_INVALID_ARG, "len must be >= 0");
+    if (!cc->have_iterate) return fail(HQ_ERR_STATE, "no solve has run");
+    hq_ctx* c = const_cast<hq_ctx*>(cc);
+    const int N = c->N, C = c->opts.buffer;
+    double pfull = 0.0, wait = 0.0, wmean = 0.0;
+    if (!c->lam_zero) {
+        try {
+            HQ_HIP(hqk::launch_scalars(c->params(c->active_fp32), 0, c->stream));
+            std::vector<double> scal(8 * (N + 1) + 8);
+            HQ_HIP(hipMemcpyAsync(scal.data(), c->d_scal, scal.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+            HQ_HIP(hipStreamSynchronize(c->stream));
+            const int L = N + 1;
+            const double mass = scal[7 * L + 1];
+            pfull = scal[3 * L + N] / mass;  // p(N): the full layer has the single state
+            wait = scal[7 * L + 3] / mass;
+            wmean = scal[7 * L + 4] / mass;
+        } catch (const HipError& e) {
+            return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+        }
+    }
+    const double rho = c->Lam / c->P64.sum_nu;
+    if (summary) {
+        summary[0] = pfull + wait;
+        summary[1] = wait;
+        summary[2] = wmean;
+        summary[3] = C == 0 ? pfull : (C > 0 ? pfull * std::pow(rho, C) : 0.0);
+    }
+    if (tail) {
+        double r = pfull;
+        for (int k = 0; k < len; ++k) {
+            r *= rho;
+            tail[k] = (C < 0 || k < C) ? r : 0.0;
+        }
     }
     return HQ_OK;
 }

@@ -56,7 +56,9 @@ struct DevScalars {
 // Everything a layer kernel needs about the instance and the layout.
 struct SweepParams {
     int N, b, H;
+    int buffer;                  // waiting room: 0 none, C > 0, -1 unlimited (Proposition 2)
     double Lam;                  // total arrival rate
+    double sum_nu;               // sum of the service rates (mu(n) for n > N)
     const double* nu;            // [N] service rates (relabelled units)
     const uint32_t* binom;       // [32*32] C(n, k) at n*32 + k
     const uint32_t* layer_off;   // [N+2] first index of layer n in the state vector

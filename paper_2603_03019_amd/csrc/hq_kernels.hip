@@ -598,26 +598,63 @@ __global__ __launch_bounds__(HQ_WG) void init_kernel(SweepParams P, LayerArgs A,
     block_partial3(acc0, acc1, 0.0, P.partials);
 }
 
-// p(n) of (10) from lambda(n), mu(n); total mass sum_m P(m); residual ratio.
+// Birth-death marginal p(n), n = 0..N, of (10) from lambda(n), mu(n), with
+// the waiting room of Proposition 2: the states with every unit busy and c
+// calls waiting carry p(N) rho^c, rho = Lambda / sum nu, for c = 1..C (or
+// every c >= 1 when unlimited).  Returns the mass of those waiting states
+// and writes their mean number of waiting calls to *wait_mean.
+__device__ double birth_death(const SweepParams& P, const double* lam, const double* mu, double* pn,
+                              double* wait_mean) {
+    const int N = P.N;
+    double g = 1.0, Z = 1.0;
+    for (int n = 1; n <= N; ++n) {
+        g = g * lam[n - 1] / mu[n];
+        Z += g;
+    }
+    const double gN = g;
+    // sum_c rho^c and sum_c c rho^c over the room
+    double s0 = 0.0, s1 = 0.0;
+    if (P.buffer != 0) {
+        const double rho = P.Lam / P.sum_nu;
+        if (P.buffer < 0) {
+            s0 = rho / (1.0 - rho);
+            s1 = rho / ((1.0 - rho) * (1.0 - rho));
+        } else {
+            double r = 1.0;
+            for (int c = 1; c <= P.buffer; ++c) {
+                r *= rho;
+                s0 += r;
+                s1 += c * r;
+            }
+        }
+    }
+    Z += gN * s0;
+    g = 1.0;
+    for (int n = 0; n <= N; ++n) {
+        if (n > 0) g = g * lam[n - 1] / mu[n];
+        pn[n] = g / Z;
+    }
+    *wait_mean = gN * s1 / Z;
+    return gN * s0 / Z;
+}
+
+// p(n) of (10) from lambda(n), mu(n); total mass (unit states and waiting
+// states); residual ratio.  misc: [0] residual, [1] mass, [2] numeric
+// flag, [3] waiting-state mass, [4] mean number waiting.
 __global__ void scalars_kernel(SweepParams P, int want_residual) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int N = P.N;
-    double g = 1.0, G = 1.0;
-    for (int n = 1; n <= N; ++n) {
-        g = g * P.sc.lam[n - 1] / P.sc.mu[n];
-        G += g;
-    }
-    g = 1.0;
-    double mass = 0.0;
+    double wmean = 0.0;
+    const double wmass = birth_death(P, P.sc.lam, P.sc.mu, P.sc.pn, &wmean);
+    double mass = wmass;
     for (int n = 0; n <= N; ++n) {
-        if (n > 0) g = g * P.sc.lam[n - 1] / P.sc.mu[n];
-        const double pn = g / G;
-        P.sc.pn[n] = pn;
         // sum_{C_n} p_n = lambda(n) / Lambda for n < N; the full layer is fixed to 1
-        mass += pn * ((n == N) ? 1.0 : P.sc.lam[n] / P.Lam);
+        mass += P.sc.pn[n] * ((n == N) ? 1.0 : P.sc.lam[n] / P.Lam);
     }
     P.sc.misc[1] = mass;
-    if (!isfinite(G)) P.sc.misc[2] = 1.0;
+    P.sc.misc[3] = wmass;
+    P.sc.misc[4] = wmean;
+    if (!isfinite(mass)) P.sc.misc[2] = 1.0;
     if (want_residual) {
         double num = 0.0, den = 0.0;
         for (int n = 0; n <= N; ++n) {
@@ -843,16 +880,8 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
             if (k < next_check && k < B.max_iters) continue;
             // residual of (1): p(n) of (10), then every layer
             if (tid == 0) {
-                double g = 1.0, G = 1.0;
-                for (int n = 1; n <= N; ++n) {
-                    g = g * s_lam[n - 1] / s_mu[n];
-                    G += g;
-                }
-                g = 1.0;
-                for (int n = 0; n <= N; ++n) {
-                    if (n > 0) g = g * s_lam[n - 1] / s_mu[n];
-                    s_pn[n] = g / G;
-                }
+                double wmean;
+                (void)birth_death(P, s_lam, s_mu, s_pn, &wmean);
             }
             __syncthreads();
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -895,16 +924,11 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
         }
         // publish the instance's scalars where the single-instance entry points read them
         if (tid == 0) {
-            double g = 1.0, G = 1.0;
-            for (int n = 1; n <= N; ++n) {
-                g = g * s_lam[n - 1] / s_mu[n];
-                G += g;
-            }
-            g = 1.0;
-            double mass = 0.0;
+            double wmean = 0.0;
+            const double wmass = birth_death(P, s_lam, s_mu, s_pn, &wmean);
+            double mass = wmass;
             for (int n = 0; n <= N; ++n) {
-                if (n > 0) g = g * s_lam[n - 1] / s_mu[n];
-                const double pn = g / G;
+                const double pn = s_pn[n];
                 P.sc.pn[n] = pn;
                 P.sc.lam[n] = s_lam[n];
                 P.sc.mu[n] = s_mu[n];
@@ -913,6 +937,8 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
             }
             P.sc.misc[0] = res;
             P.sc.misc[1] = mass;
+            P.sc.misc[3] = wmass;
+            P.sc.misc[4] = wmean;
             P.sc.misc[2] = (status == HQ_ERR_NUMERIC_CODE) ? 1.0 : 0.0;
             BatchOut o;
             o.iterations = k;

@@ -23,12 +23,13 @@ HQ_FP64, HQ_FP32, HQ_FP32_POLISH64 = 0, 1, 2
 HQ_INNER_CLOSED, HQ_INNER_ONE = 0, 1
 HQ_INIT_UNIFORM, HQ_INIT_PRODUCT, HQ_INIT_STATE, HQ_INIT_LEARNED = 0, 1, 2, 3
 HQ_STOP_RESIDUAL, HQ_STOP_DELTA = 0, 1
+HQ_BUFFER_UNLIMITED, HQ_BUFFER_MAX = -1, 65536
 
 STATUS_NAMES = {0: "HQ_OK", 1: "HQ_ERR_INVALID_ARG", 2: "HQ_ERR_OUT_OF_MEMORY", 3: "HQ_ERR_DEVICE",
                 4: "HQ_ERR_NOT_CONVERGED", 5: "HQ_ERR_NUMERIC", 6: "HQ_ERR_STATE"}
 
 # every symbol include/hq.h declares
-EXPORTED = ["hq_default_options", "hq_create", "hq_solve", "hq_marginals", "hq_state", "hq_solve_batch",
+EXPORTED = ["hq_default_options", "hq_create", "hq_solve", "hq_marginals", "hq_queue", "hq_state", "hq_solve_batch",
             "hq_destroy", "hq_last_error", "hq_iterate", "hq_reset", "hq_residual", "hq_conditional",
             "hq_layer_scalars", "hq_state_device", "hq_num_units", "hq_mlp_features", "hq_mlp_create",
             "hq_mlp_destroy", "hq_mlp_get_params", "hq_mlp_set_params", "hq_mlp_forward", "hq_mlp_gradient",
@@ -49,7 +50,7 @@ class hq_options(ctypes.Structure):
                 ("tile_bits", ctypes.c_int), ("device", ctypes.c_int), ("stored_layers", ctypes.c_int),
                 ("init_rho", ctypes.POINTER(ctypes.c_double)),
                 ("init_state", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
-                ("mlp", ctypes.c_void_p)]
+                ("mlp", ctypes.c_void_p), ("buffer", ctypes.c_int)]
 
 
 class hq_info(ctypes.Structure):
@@ -85,6 +86,8 @@ def load(path: str = LIB_PATH):
     L.hq_solve.restype = c_int
     L.hq_marginals.argtypes = [vp, dp, dp]
     L.hq_marginals.restype = c_int
+    L.hq_queue.argtypes = [vp, dp, dp, c_int]
+    L.hq_queue.restype = c_int
     L.hq_state.argtypes = [vp, dp]
     L.hq_state.restype = c_int
     L.hq_solve_batch.argtypes = [ctypes.POINTER(vp), c_int, c_double, ctypes.POINTER(hq_info)]
@@ -214,6 +217,16 @@ def hq_marginals(ctx: Context):
     pn = np.zeros(ctx.N + 1)
     _check(load().hq_marginals(ctx.handle, _dptr(rho), _dptr(pn)))
     return rho, pn
+
+
+def hq_queue(ctx: Context, length: int = 0):
+    """Waiting-room measures: (summary[4], tail[length]) with summary =
+    (P(all busy), P(a call waits), mean waiting, P(arrival lost)) and
+    tail[c-1] = P~{c}."""
+    summ = np.zeros(4)
+    tail = np.zeros(length)
+    _check(load().hq_queue(ctx.handle, _dptr(summ), _dptr(tail) if length else None, int(length)))
+    return summ, tail
 
 
 def hq_state(ctx: Context) -> np.ndarray:

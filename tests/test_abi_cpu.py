@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_options():
     o = hq.hq_default_options()
-    assert o.precision == hq.HQ_FP64 and o.inner == hq.HQ_INNER_CLOSED and o.init == hq.HQ_INIT_UNIFORM
+    assert o.precision == hq.HQ_FP64 and o.inner == hq.HQ_INNER_ONE and o.init == hq.HQ_INIT_UNIFORM
+    assert o.buffer == 0
     assert o.max_iters == 100000 and o.device == -1 and not o.stream
 
 
@@ -43,7 +44,8 @@ def _ok_args(N=4, J=3):
 
 @pytest.mark.parametrize("case", ["N0", "Nbig", "J0", "neg_lambda", "nan_lambda", "zero_mu", "inf_mu",
                                   "not_perm", "out_of_range", "bad_precision", "bad_inner", "product_no_rho",
-                                  "state_no_state", "bad_rho", "bad_tile"])
+                                  "state_no_state", "bad_rho", "bad_tile", "bad_buffer", "big_buffer",
+                                  "unstable_room"])
 def test_invalid_arguments_rejected_on_host(case):
     N, J, lam, mu, pref = _ok_args()
     kw = {}
@@ -89,6 +91,13 @@ def test_invalid_arguments_rejected_on_host(case):
         kw["init_rho"] = np.array([0.5, 1.5, 0.2, 0.1])
     elif case == "bad_tile":
         kw["tile_bits"] = 13
+    elif case == "bad_buffer":
+        kw["buffer"] = -2
+    elif case == "big_buffer":
+        kw["buffer"] = hq.HQ_BUFFER_MAX + 1
+    elif case == "unstable_room":
+        kw["buffer"] = hq.HQ_BUFFER_UNLIMITED
+        lam = lam * (4.0 / lam.sum())  # Lambda = sum of the service rates
     with pytest.raises(hq.HQError) as e:
         hq.hq_create(N, J, lam, mu, pref, **kw)
     assert e.value.status == hq.HQ_ERR_INVALID_ARG
@@ -99,6 +108,7 @@ def test_null_arguments():
     L = hq.load()
     assert L.hq_solve(None, 1e-8, None) == hq.HQ_ERR_INVALID_ARG
     assert L.hq_marginals(None, None, None) == hq.HQ_ERR_INVALID_ARG
+    assert L.hq_queue(None, None, None, 0) == hq.HQ_ERR_INVALID_ARG
     assert L.hq_state(None, None) == hq.HQ_ERR_INVALID_ARG
     assert L.hq_iterate(None, 1) == hq.HQ_ERR_INVALID_ARG
     assert L.hq_num_units(None) == 0
