@@ -65,6 +65,8 @@ def lib():
         L.orc_threads.restype = ctypes.c_int
         L.orc_birth_death.restype = ctypes.c_int
         L.orc_birth_death.argtypes = [ctypes.c_int, d, d, ctypes.c_double, ctypes.c_double, ctypes.c_int, d, d, d]
+        L.orc_dispatch.restype = None
+        L.orc_dispatch.argtypes = [ctypes.c_int, ctypes.c_int, i32, d, d]
         L.orc_balance_terms.restype = None
         L.orc_balance_terms.argtypes = [ctypes.c_int, ctypes.c_int, d, d, i32, ctypes.c_longlong, u32, d, d, d]
         _lib = L
@@ -249,3 +251,19 @@ def buffered_state(res: OracleResult, inst, C: int):
         scale[n] = p[n] / res.p_n[n] if res.p_n[n] > 0 else 0.0
     pop = np.array([bin(m).count("1") for m in range(1 << inst.N)])
     return res.P * scale[pop], tail, summ
+
+
+def dispatch(inst, P: np.ndarray) -> np.ndarray:
+    """q[j, u]: probability that a call from node j is sent to unit u
+    (first idle unit of its list), from P in bitmask order."""
+    _, _, pref = _args(inst)
+    q = np.zeros(inst.J * inst.N)
+    lib().orc_dispatch(inst.N, inst.J, _ip(pref), _dp(np.ascontiguousarray(P, dtype=np.float64)), _dp(q))
+    return q.reshape(inst.J, inst.N)
+
+
+def mean_travel(inst, q: np.ndarray, travel: np.ndarray) -> float:
+    """Mean travel time of dispatched calls: sum_j lambda_j sum_u q_ju t_ju
+    over sum_j lambda_j sum_u q_ju (travel[j, u] from unit u to node j)."""
+    w = inst.lam[:, None] * q
+    return float((w * travel).sum() / w.sum())

@@ -610,3 +610,31 @@ int orc_birth_death(int N, const double* lamn, const double* mun, double Lam, do
     free(g);
     return 0;
 }
+
+/*
+ * Dispatch probabilities of the loss system (the performance measures named
+ * in Section 1: unit workloads and response times): for a call from node j,
+ * the probability that unit u is the one sent, i.e. that u is the first
+ * unit of node j's list that is idle.  Arrivals see time averages, so
+ *   q[j * N + u] = sum_m P(m) [first idle unit of pref row j in m is u].
+ * Brute force over every state and node, O(2^N J N).  sum_u q[j * N + u] is
+ * 1 - P(all busy).
+ */
+void orc_dispatch(int N, int J, const int32_t* pref, const double* P, double* q) {
+    const uint32_t S = 1u << N;
+    memset(q, 0, sizeof(double) * (size_t)J * N);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int j = 0; j < J; ++j) {
+        const int32_t* row = pref + (size_t)j * N;
+        double* qj = q + (size_t)j * N;
+        for (uint32_t m = 0; m < S; ++m) {
+            for (int h = 0; h < N; ++h) {
+                const int u = row[h];
+                if (!((m >> u) & 1u)) {
+                    qj[u] += P[m];
+                    break;
+                }
+            }
+        }
+    }
+}

@@ -460,3 +460,41 @@ def test_unlimited_room_erlang_c_and_limit():
     with pytest.raises(ValueError):
         over = inst.__class__(**{**inst.__dict__, "lam": inst.lam * 2.0})
         cpu.birth_death(cpu.solve(over, tol=1e-10), over, -1)
+
+
+# ---------------------------------------------------------------------------
+# Dispatch probabilities (unit workloads, response times)
+# ---------------------------------------------------------------------------
+def test_dispatch_flow_balance_against_dense_solve():
+    # a unit's dispatch rate equals its completion rate nu_u rho_u, an exact
+    # identity of the stationary law; P from LU, q from the brute-force oracle
+    inst = config_instance(1, 7, N=8, J=25)
+    P = exact.dense_solve(inst)
+    q = cpu.dispatch(inst, P)
+    full = P[-1]
+    np.testing.assert_allclose(q.sum(axis=1), 1.0 - full, rtol=1e-12)
+    rho = np.array([P[[m for m in range(1 << inst.N) if (m >> u) & 1]].sum() for u in range(inst.N)])
+    np.testing.assert_allclose((inst.lam[:, None] * q).sum(axis=0), inst.nu * rho, rtol=1e-10)
+
+
+def test_dispatch_ordered_hunting_closed_form():
+    # one shared list, equal rates: the first h units form M/M/h/h, so the
+    # (h+1)-th choice gets the calls that find h busy and it idle
+    N = 7
+    inst = config_instance(1, 8, N=N, J=5, homogeneous=True)
+    row = inst.pref[0].copy()
+    inst = inst.__class__(**{**inst.__dict__, "pref": np.tile(row, (inst.J, 1))})
+    a = float(np.sum(inst.lam)) / float(inst.nu[0])
+    P = exact.dense_solve(inst)
+    q = cpu.dispatch(inst, P)
+    B = [1.0] + [exact.erlang_b(h, a) for h in range(1, N + 1)]
+    for h in range(N):
+        np.testing.assert_allclose(q[:, row[h]], B[h] - B[h + 1], rtol=1e-10)
+
+
+def test_mean_travel_definition():
+    inst = config_instance(1, 9, N=6, J=10)
+    P = exact.dense_solve(inst)
+    q = cpu.dispatch(inst, P)
+    t = np.ones((inst.J, inst.N)) * 3.5
+    assert cpu.mean_travel(inst, q, t) == pytest.approx(3.5, rel=1e-14)
