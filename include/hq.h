@@ -173,6 +173,29 @@ hq_status hq_marginals(const hq_ctx* ctx, double* rho_u, double* p_n);
  */
 hq_status hq_queue(const hq_ctx* ctx, double* summary, double* tail, int len);
 
+/*
+ * Dispatch measures of the last iterate: unit workloads and response times,
+ * the performance measures the stationary law serves (Section 1).  A call
+ * from node j is sent to the first unit of its list that is idle (eq. (3)),
+ * so with G(S) = sum over states m containing S of P(m),
+ *   q[j * N + i] = G(units ranked before i by j) - G(those and i),
+ * the probability that a call from node j is sent to unit i on arrival.
+ * Computed on the device: P in bitmask order, an in-place superset-sum
+ * transform over all N bits, one pass of reads per node.
+ *   travel      [J*N] (nullable) travel time to node j from unit i at
+ *               [j * N + i], finite; unit labels as in pref_lists
+ *   q           [J*N] (nullable) out, as above; sum_i q[j * N + i] is the
+ *               probability that some unit is idle (1 - P(full) without a
+ *               waiting room; calls that wait are not counted)
+ *   mean_travel (nullable) out: mean travel time of the calls sent on
+ *               arrival, sum_j lambda_j sum_i q t / sum_j lambda_j sum_i q
+ *               (needs travel)
+ * Allocates 2^N doubles of device memory on the first call (kept until
+ * hq_destroy).  Errors: HQ_ERR_INVALID_ARG, HQ_ERR_STATE before any solve,
+ * HQ_ERR_OUT_OF_MEMORY, HQ_ERR_DEVICE.
+ */
+hq_status hq_dispatch(const hq_ctx* ctx, const double* travel, double* q, double* mean_travel);
+
 /* Export P [2^N] (bitmask order, renormalised to sum 1) to host memory.
  * HQ_ERR_STATE before any solve. */
 hq_status hq_state(const hq_ctx* ctx, double* P);

@@ -31,6 +31,8 @@ hipError_t launch_export(bool fp32, const SweepParams& P, const LayerArgs& A, co
                          const uint32_t* orig_bit, int conditional, hipStream_t s);
 hipError_t launch_marginal(bool fp32, const SweepParams& P, const LayerArgs& A, const void* x, double* part,
                            double* rho, hipStream_t s);
+hipError_t launch_dispatch(double* G, int N, int J, const int32_t* pref, double* q, const double* lam,
+                           const double* travel, double* sums, hipStream_t s);
 hipError_t launch_widen(const float* src, double* dst, uint32_t begin, uint32_t count, double factor,
                         hipStream_t s);
 hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, uint32_t nnodes, hipStream_t s);
@@ -100,6 +102,8 @@ struct hq_ctx {
     std::vector<double> state_init;  // original bitmask order
     std::vector<int> orig;           // new label -> original unit
     std::vector<double> nu;          // relabelled service rates
+    std::vector<double> lam_in;      // lambda_j as given
+    std::vector<int32_t> pref_in;    // preference lists as given (original unit labels)
     std::vector<TrieNode> nodes;
     size_t max_groups = 0;
     std::vector<LayerArgs> layers;   // per layer n = 0..N
@@ -115,6 +119,10 @@ struct hq_ctx {
              *d_orig_bit = nullptr, *d_seg_desc = nullptr, *d_segoff = nullptr, *d_seg_prog = nullptr;
     ProgTerm* d_prog = nullptr;
     size_t prog_terms = 0;
+    // dispatch measures (allocated on first use)
+    double *d_G = nullptr, *d_q = nullptr, *d_lam_in = nullptr, *d_travel = nullptr, *d_tsum = nullptr;
+    int32_t* d_pref_in = nullptr;
+    bool dispatch_ready = false;
     double* d_coefs = nullptr;
     int stored_from = -1;  // first layer with stored coefficients (-1: none)
     uint16_t *d_lo_unrank = nullptr, *d_lo_rank = nullptr;
@@ -131,7 +139,8 @@ struct hq_ctx {
         void* ptrs[] = {x64,       x32,        d_nu,       d_mu_lo,    d_tcoef,     d_scal,     d_part,
                         d_scale64, d_scale32,  d_rho,      d_xu,       d_given,     d_binom,    d_layer_off,
                         d_lo_qstart, d_prog_off, d_prog, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
-                        d_counters, d_seg_desc, d_segoff,   d_coefs,     d_seg_prog};
+                        d_counters, d_seg_desc, d_segoff,   d_coefs,     d_seg_prog, d_G,
+                        d_q,       d_lam_in,   d_travel,   d_tsum,     d_pref_in};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         x64 = nullptr;
@@ -454,6 +463,8 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     if (c->H > HQ_MAXH) return fail(HQ_ERR_INVALID_ARG, "tile_bits too small for this N");
 
     // relabel units (new label u <-> original unit orig[u])
+    c->lam_in.assign(lam, lam + J);
+    c->pref_in.assign(pref, pref + (size_t)J * N);
     c->orig = relabel(N, J, lam, mu, pref);
     std::vector<int> newlab(N);
     for (int u = 0; u < N; ++u) newlab[c->orig[u]] = u;
@@ -1283,6 +1294,53 @@ hq_status hq_marginals(const hq_ctx* cc, double* rho_u, double* p_n) {
             }
             p_n[N] += wait;
         }
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+    return HQ_OK;
+}
+
+hq_status hq_dispatch(const hq_ctx* cc, const double* travel, double* q, double* mean_travel) {
+    if (!cc) return fail(HQ_ERR_INVALID_ARG, "ctx is NULL");
+    if (mean_travel && !travel) return fail(HQ_ERR_INVALID_ARG, "mean_travel needs travel");
+    if (!cc->have_iterate) return fail(HQ_ERR_STATE, "no solve has run");
+    hq_ctx* c = const_cast<hq_ctx*>(cc);
+    const int N = c->N, J = c->J;
+    const size_t JN = (size_t)J * N;
+    if (travel)
+        for (size_t i = 0; i < JN; ++i)
+            if (!std::isfinite(travel[i])) return fail(HQ_ERR_INVALID_ARG, "travel times must be finite");
+    if (c->lam_zero) {
+        // every unit idle: each call goes to its first choice (no call has a rate)
+        std::vector<double> q0(JN, 0.0);
+        for (int j = 0; j < J; ++j) q0[(size_t)j * N + c->pref_in[(size_t)j * N]] = 1.0;
+        if (q) std::copy(q0.begin(), q0.end(), q);
+        if (mean_travel) *mean_travel = 0.0;
+        return HQ_OK;
+    }
+    try {
+        if (!c->dispatch_ready) {
+            if (!c->d_G) c->d_G = dalloc<double>(c->states());
+            if (!c->d_q) c->d_q = dalloc<double>(JN);
+            if (!c->d_lam_in) c->d_lam_in = dalloc<double>(J);
+            if (!c->d_travel) c->d_travel = dalloc<double>(JN);
+            if (!c->d_tsum) c->d_tsum = dalloc<double>(2);
+            if (!c->d_pref_in) c->d_pref_in = dalloc<int32_t>(JN);
+            h2d(c->d_lam_in, c->lam_in, c->stream);
+            h2d(c->d_pref_in, c->pref_in, c->stream);
+            c->dispatch_ready = true;
+        }
+        if (travel) HQ_HIP(hipMemcpyAsync(c->d_travel, travel, JN * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        export_impl(c, c->d_G, 0, c->stream);
+        HQ_HIP(hqk::launch_dispatch(c->d_G, N, J, c->d_pref_in, c->d_q, c->d_lam_in, travel ? c->d_travel : nullptr,
+                                    c->d_tsum, c->stream));
+        double sums[2] = {0.0, 0.0};
+        if (q) HQ_HIP(hipMemcpyAsync(q, c->d_q, JN * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (mean_travel) HQ_HIP(hipMemcpyAsync(sums, c->d_tsum, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HQ_HIP(hipStreamSynchronize(c->stream));
+        if (mean_travel) *mean_travel = sums[1] > 0.0 ? sums[0] / sums[1] : 0.0;
+    } catch (const std::bad_alloc&) {
+        return fail(HQ_ERR_OUT_OF_MEMORY, "device allocation failed");
     } catch (const HipError& e) {
         return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
     }

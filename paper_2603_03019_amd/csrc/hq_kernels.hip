@@ -951,6 +951,87 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Dispatch probabilities (unit workloads and response times).  A call from
+// node j goes to unit pi_j[h] iff pi_j[0..h-1] are busy and pi_j[h] is
+// idle, so with G(S) = sum_{m superset of S} P(m) (superset sums of P),
+//   q_j(pi_j[h]) = G(prefix of length h) - G(prefix of length h + 1).
+// G comes from an in-place superset-sum transform of P over all N bits, a
+// few bits per pass.
+// ---------------------------------------------------------------------------
+// One pass over bits [L, L + M): thread (hi, lo) holds the 2^M entries
+// hi * 2^(L+M) + mid * 2^L + lo in registers; consecutive threads take
+// consecutive lo, so loads coalesce once 2^L >= 64.
+template <int M>
+__global__ __launch_bounds__(256) void zeta_kernel(double* __restrict__ G, int N, int L) {
+    const unsigned long long total = 1ull << (N - M);
+    const unsigned long long t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const unsigned long long lo = t & ((1ull << L) - 1ull), hi = t >> L;
+    const unsigned long long base = (hi << (L + M)) + lo, stride = 1ull << L;
+    double v[1 << M];
+#pragma unroll
+    for (int k = 0; k < (1 << M); ++k) v[k] = G[base + (unsigned long long)k * stride];
+#pragma unroll
+    for (int bit = 0; bit < M; ++bit)
+#pragma unroll
+        for (int k = 0; k < (1 << M); ++k)
+            if (!((k >> bit) & 1)) v[k] += v[k | (1 << bit)];
+#pragma unroll
+    for (int k = 0; k < (1 << M); ++k) G[base + (unsigned long long)k * stride] = v[k];
+}
+
+// q[j * N + u] for every node j (one thread each), from the superset sums.
+__global__ __launch_bounds__(256) void dispatch_kernel(const double* __restrict__ G, int N, int J,
+                                                       const int32_t* __restrict__ pref, double* __restrict__ q) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= J) return;
+    const int32_t* row = pref + (size_t)j * N;
+    double* qj = q + (size_t)j * N;
+    uint32_t S = 0u;
+    double gs = G[0];
+    for (int h = 0; h < N; ++h) {
+        const int u = row[h];
+        const uint32_t S2 = S | (1u << u);
+        const double g2 = G[S2];
+        qj[u] = gs - g2;
+        S = S2;
+        gs = g2;
+    }
+}
+
+// sums[0] = sum_j lambda_j sum_u q_ju t_ju, sums[1] = sum_j lambda_j sum_u
+// q_ju, in a fixed order (one work-group).
+__global__ __launch_bounds__(256) void travel_kernel(const double* __restrict__ q, const double* __restrict__ lam,
+                                                     const double* __restrict__ travel, int N, int J,
+                                                     double* __restrict__ sums) {
+    __shared__ double s_a[4], s_b[4];
+    double a = 0.0, b = 0.0;
+    const size_t total = (size_t)J * N;
+    for (size_t i = threadIdx.x; i < total; i += blockDim.x) {
+        const double w = lam[i / N] * q[i];
+        a += w * travel[i];
+        b += w;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_a[w] = a;
+        s_b[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+        for (int i = 0; i < 4; ++i) {
+            x += s_a[i];
+            y += s_b[i];
+        }
+        sums[0] = x;
+        sums[1] = y;
+    }
+}
+
 __global__ void reset_counter_kernel(unsigned int* c) {
     if (threadIdx.x == 0) *c = 0u;
 }
@@ -1098,6 +1179,26 @@ hipError_t launch_batch(bool fp32, int block, const BatchItem* items, BatchOut* 
             return hipErrorInvalidValue;
     }
 #undef HQ_BATCH_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_dispatch(double* G, int N, int J, const int32_t* pref, double* q, const double* lam,
+                           const double* travel, double* sums, hipStream_t s) {
+    for (int L = 0; L < N;) {
+        const int M = N - L < 5 ? N - L : 5;
+        const unsigned long long threads = 1ull << (N - M);
+        const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+        switch (M) {
+            case 1: hipLaunchKernelGGL(zeta_kernel<1>, grid, block, 0, s, G, N, L); break;
+            case 2: hipLaunchKernelGGL(zeta_kernel<2>, grid, block, 0, s, G, N, L); break;
+            case 3: hipLaunchKernelGGL(zeta_kernel<3>, grid, block, 0, s, G, N, L); break;
+            case 4: hipLaunchKernelGGL(zeta_kernel<4>, grid, block, 0, s, G, N, L); break;
+            default: hipLaunchKernelGGL(zeta_kernel<5>, grid, block, 0, s, G, N, L); break;
+        }
+        L += M;
+    }
+    hipLaunchKernelGGL(dispatch_kernel, dim3((J + 255) / 256), dim3(256), 0, s, (const double*)G, N, J, pref, q);
+    if (travel) hipLaunchKernelGGL(travel_kernel, dim3(1), dim3(256), 0, s, (const double*)q, lam, travel, N, J, sums);
     return hipGetLastError();
 }
 

@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "HQ_OK", 1: "HQ_ERR_INVALID_ARG", 2: "HQ_ERR_OUT_OF_MEMORY", 
                 4: "HQ_ERR_NOT_CONVERGED", 5: "HQ_ERR_NUMERIC", 6: "HQ_ERR_STATE"}
 
 # every symbol include/hq.h declares
-EXPORTED = ["hq_default_options", "hq_create", "hq_solve", "hq_marginals", "hq_queue", "hq_state", "hq_solve_batch",
+EXPORTED = ["hq_default_options", "hq_create", "hq_solve", "hq_marginals", "hq_queue", "hq_dispatch", "hq_state",
+            "hq_solve_batch",
             "hq_destroy", "hq_last_error", "hq_iterate", "hq_reset", "hq_residual", "hq_conditional",
             "hq_layer_scalars", "hq_state_device", "hq_num_units", "hq_mlp_features", "hq_mlp_create",
             "hq_mlp_destroy", "hq_mlp_get_params", "hq_mlp_set_params", "hq_mlp_forward", "hq_mlp_gradient",
@@ -88,6 +89,8 @@ def load(path: str = LIB_PATH):
     L.hq_marginals.restype = c_int
     L.hq_queue.argtypes = [vp, dp, dp, c_int]
     L.hq_queue.restype = c_int
+    L.hq_dispatch.argtypes = [vp, dp, dp, dp]
+    L.hq_dispatch.restype = c_int
     L.hq_state.argtypes = [vp, dp]
     L.hq_state.restype = c_int
     L.hq_solve_batch.argtypes = [ctypes.POINTER(vp), c_int, c_double, ctypes.POINTER(hq_info)]
@@ -156,9 +159,10 @@ def hq_default_options() -> hq_options:
 class Context:
     """Owns an hq_ctx*; the arrays referenced by its options are kept alive."""
 
-    def __init__(self, handle: ctypes.c_void_p, N: int):
+    def __init__(self, handle: ctypes.c_void_p, N: int, J: int = 0):
         self.handle = handle
         self.N = N
+        self.J = J
 
     def __del__(self):
         try:
@@ -202,7 +206,7 @@ def hq_create(N: int, J: int, lambda_j, mu_i, pref_lists, opts: Optional[hq_opti
     h = ctypes.c_void_p()
     _check(L.hq_create(int(N), int(J), _dptr(lam), _dptr(mu), pref.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                        ctypes.byref(o), ctypes.byref(h)))
-    return Context(h, int(N))
+    return Context(h, int(N), int(J))
 
 
 def hq_solve(ctx: Context, tol: float, *, allow_not_converged: bool = False) -> dict:
@@ -217,6 +221,19 @@ def hq_marginals(ctx: Context):
     pn = np.zeros(ctx.N + 1)
     _check(load().hq_marginals(ctx.handle, _dptr(rho), _dptr(pn)))
     return rho, pn
+
+
+def hq_dispatch(ctx: Context, travel=None):
+    """(q[J, N], mean travel time or None): q[j, i] = probability that a
+    call from node j is sent to unit i; travel[j, i] = travel time from
+    unit i to node j."""
+    q = np.zeros(ctx.J * ctx.N)
+    t = None if travel is None else np.ascontiguousarray(travel, dtype=np.float64).reshape(-1)
+    if t is not None and t.size != ctx.J * ctx.N:
+        raise HQError(HQ_ERR_INVALID_ARG, "travel must have J * N entries")
+    mt = ctypes.c_double(0.0)
+    _check(load().hq_dispatch(ctx.handle, _dptr(t), _dptr(q), ctypes.byref(mt) if t is not None else None))
+    return q.reshape(ctx.J, ctx.N), (mt.value if t is not None else None)
 
 
 def hq_queue(ctx: Context, length: int = 0):
