@@ -61,8 +61,10 @@ enum {
 
 /* reading of Algorithm 1's inner mu(n) loop (delta is never stated) */
 enum {
-    HQ_INNER_CLOSED = 0, /* the delta -> 0 limit: mu(n) = B / (1 - A) each layer (two passes) */
-    HQ_INNER_ONE = 1     /* one update per layer (delta = infinity); same fixed point */
+    HQ_INNER_CLOSED = 0,  /* the delta -> 0 limit: mu(n) = B / (1 - A) each layer (two passes) */
+    HQ_INNER_ONE = 1,     /* one update per layer (delta = infinity); same fixed point */
+    HQ_INNER_LITERAL = 2  /* the inner loop of Algorithm 1 as written, tolerance opts.delta
+                             (two passes; the loop itself runs on the layer's sums) */
 };
 
 /* initial iterate */
@@ -81,7 +83,7 @@ enum {
 
 typedef struct {
     int precision;            /* HQ_FP64 | HQ_FP32 | HQ_FP32_POLISH64 */
-    int inner;                /* HQ_INNER_CLOSED | HQ_INNER_ONE */
+    int inner;                /* HQ_INNER_CLOSED | HQ_INNER_ONE | HQ_INNER_LITERAL */
     int init;                 /* HQ_INIT_* */
     int stop;                 /* HQ_STOP_* */
     int max_iters;            /* <= 0: default 100000 */
@@ -99,6 +101,8 @@ typedef struct {
                                  Proposition 2): 0 = none (loss system), 0 < C <= HQ_BUFFER_MAX =
                                  at most C waiting calls, HQ_BUFFER_UNLIMITED = no limit (needs
                                  Lambda < sum mu_i) */
+    double delta;             /* tolerance of the inner loop for HQ_INNER_LITERAL (finite, > 0;
+                                 the loop stops when max_m |p^{r} - p^{r-1}| <= delta) */
 } hq_options;
 
 typedef struct {
@@ -196,15 +200,18 @@ hq_status hq_queue(const hq_ctx* ctx, double* summary, double* tail, int len);
  */
 hq_status hq_dispatch(const hq_ctx* ctx, const double* travel, double* q, double* mean_travel);
 
-/* Export P [2^N] (bitmask order, renormalised to sum 1) to host memory.
- * HQ_ERR_STATE before any solve. */
+/* Export P [2^N] (bitmask order, renormalised so that the whole system sums
+ * to 1: with a waiting room the unit states sum to 1 - P(a call waits)) to
+ * host memory.  HQ_ERR_STATE before any solve. */
 hq_status hq_state(const hq_ctx* ctx, double* P);
 
 /*
  * Solve several instances (an uneven batch of candidate deployments) to tol
  * in one persistent launch (Section 3 iteration per instance, independent
  * instances).  Every context must be on the same device and must have been
- * created with HQ_FP64 or HQ_FP32 storage.  infos (nullable) [count].
+ * created with HQ_FP64 or HQ_FP32 storage, the residual stopping rule and the
+ * closed or one-update inner form (HQ_ERR_INVALID_ARG otherwise).  infos
+ * (nullable) [count].
  * Returns HQ_OK only if every instance converged; per-instance statuses are
  * in infos.
  */

@@ -380,6 +380,7 @@ void setup_params(hq_ctx* c) {
     P.b = c->b;
     P.H = c->H;
     P.buffer = c->opts.buffer;
+    P.delta = c->opts.delta;
     P.Lam = c->Lam;
     P.sum_nu = 0.0;
     for (int u = 0; u < c->N; ++u) P.sum_nu += c->nu[u];
@@ -426,7 +427,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     if (opts) o = *opts;
     if (o.precision < HQ_FP64 || o.precision > HQ_FP32_POLISH64)
         return fail(HQ_ERR_INVALID_ARG, "unknown precision");
-    if (o.inner != HQ_INNER_CLOSED && o.inner != HQ_INNER_ONE) return fail(HQ_ERR_INVALID_ARG, "unknown inner mode");
+    if (o.inner != HQ_INNER_CLOSED && o.inner != HQ_INNER_ONE && o.inner != HQ_INNER_LITERAL)
+        return fail(HQ_ERR_INVALID_ARG, "unknown inner mode");
+    if (o.inner == HQ_INNER_LITERAL && !(o.delta > 0.0 && std::isfinite(o.delta)))
+        return fail(HQ_ERR_INVALID_ARG, "HQ_INNER_LITERAL needs a finite delta > 0");
     if (o.init < HQ_INIT_UNIFORM || o.init > HQ_INIT_LEARNED) return fail(HQ_ERR_INVALID_ARG, "unknown init mode");
     if (o.init == HQ_INIT_LEARNED && !o.mlp) return fail(HQ_ERR_INVALID_ARG, "HQ_INIT_LEARNED needs opts.mlp");
     if (o.stop != HQ_STOP_RESIDUAL && o.stop != HQ_STOP_DELTA) return fail(HQ_ERR_INVALID_ARG, "unknown stop rule");
@@ -687,11 +691,13 @@ void run_init(hq_ctx* c, bool fp32) {
 
 void run_sweep(hq_ctx* c, bool track_delta) {
     const bool fp32 = c->active_fp32;
-    const int one = c->opts.inner == HQ_INNER_ONE ? 1 : 0;
+    const int inner = c->opts.inner;  // 0 closed, 1 one update, 2 literal loop
     for (int n = 1; n <= c->N - 1; ++n) {
         const LayerArgs& A = c->layers[n];
-        if (!one) HQ_HIP(hqk::launch_layer(M_PASS1, false, fp32, c->params(fp32), A, c->xbuf(fp32), one, c->stream));
-        HQ_HIP(hqk::launch_layer(M_WRITE, track_delta, fp32, c->params(fp32), A, c->xbuf(fp32), one, c->stream));
+        if (inner != HQ_INNER_ONE)
+            HQ_HIP(hqk::launch_layer(M_PASS1, inner == HQ_INNER_LITERAL, fp32, c->params(fp32), A, c->xbuf(fp32),
+                                     inner, c->stream));
+        HQ_HIP(hqk::launch_layer(M_WRITE, track_delta, fp32, c->params(fp32), A, c->xbuf(fp32), inner, c->stream));
     }
     c->iterations_done++;
 }
@@ -1065,6 +1071,8 @@ hq_status batch_impl(hq_ctx* const* ctxs, int count, double tol, hq_info* infos)
             return fail(HQ_ERR_INVALID_ARG, "batched solves take HQ_FP64 or HQ_FP32 contexts");
         if (c->opts.stop != HQ_STOP_RESIDUAL)
             return fail(HQ_ERR_INVALID_ARG, "batched solves use the residual stopping rule");
+        if (c->opts.inner == HQ_INNER_LITERAL)
+            return fail(HQ_ERR_INVALID_ARG, "batched solves take the closed or one-update inner form");
     }
     hq_status worst = HQ_OK;
     for (int i = 0; i < count; ++i) {

@@ -8,7 +8,7 @@
 #define HQ_MAXB 12          // largest low-bit tile width b
 #define HQ_MAXH 26          // largest high-bit count H = N - b
 #define HQ_WG 256           // threads per work-group of the layer kernels
-#define HQ_NPART 3          // partial sums per work-group of the layer kernels
+#define HQ_NPART 4          // partials per work-group of the layer kernels (sum, sum, max, max)
 #ifndef HQ_HCHUNK
 #define HQ_HCHUNK 8         // independent high-unit neighbour loads issued together
 #endif
@@ -59,6 +59,7 @@ struct SweepParams {
     int buffer;                  // waiting room: 0 none, C > 0, -1 unlimited (Proposition 2)
     double Lam;                  // total arrival rate
     double sum_nu;               // sum of the service rates (mu(n) for n > N)
+    double delta;                // tolerance of the literal inner loop
     const double* nu;            // [N] service rates (relabelled units)
     const uint32_t* binom;       // [32*32] C(n, k) at n*32 + k
     const uint32_t* layer_off;   // [N+2] first index of layer n in the state vector

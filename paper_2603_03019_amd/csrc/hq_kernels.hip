@@ -84,65 +84,74 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Reduce three per-thread values over the work-group (sum, sum, max) and
-// store them as this work-group's partial.  No fence: the finalize kernel
-// that reads the partials runs after this kernel on the same stream.
-__device__ void block_partial3(double a0, double a1, double a2, double* partials) {
-    __shared__ double s_red[3][HQ_WG / 64];
+// Reduce four per-thread values over the work-group (sum, sum, max, max)
+// and store them as this work-group's partial.  No fence: the finalize
+// kernel that reads the partials runs after this kernel on the same stream.
+__device__ void block_partial(double a0, double a1, double a2, double a3, double* partials) {
+    __shared__ double s_red[4][HQ_WG / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
     a2 = wave_max(a2);
+    a3 = wave_max(a3);
     if (lane == 0) {
         s_red[0][w] = a0;
         s_red[1][w] = a1;
         s_red[2][w] = a2;
+        s_red[3][w] = a3;
     }
     __syncthreads();
     if (tid == 0) {
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
         for (int i = 0; i < HQ_WG / 64; ++i) {
             b0 += s_red[0][i];
             b1 += s_red[1][i];
             b2 = fmax(b2, s_red[2][i]);
+            b3 = fmax(b3, s_red[3][i]);
         }
         double* pp = partials + (size_t)blockIdx.x * HQ_NPART;
         pp[0] = b0;
         pp[1] = b1;
         pp[2] = b2;
+        pp[3] = b3;
     }
 }
 
-// Fixed-order sum of `count` partial triples by one work-group.
-__device__ void sum_partials3(const double* partials, uint32_t count, double out[3]) {
-    __shared__ double s_red[3][HQ_WG / 64];
+// Fixed-order reduction of `count` partials by one work-group.
+__device__ void sum_partials(const double* partials, uint32_t count, double out[4]) {
+    __shared__ double s_red[4][HQ_WG / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
     for (uint32_t i = tid; i < count; i += HQ_WG) {
         const double* pp = partials + (size_t)i * HQ_NPART;
         c0 += pp[0];
         c1 += pp[1];
         c2 = fmax(c2, pp[2]);
+        c3 = fmax(c3, pp[3]);
     }
     c0 = wave_sum(c0);
     c1 = wave_sum(c1);
     c2 = wave_max(c2);
+    c3 = wave_max(c3);
     if (lane == 0) {
         s_red[0][w] = c0;
         s_red[1][w] = c1;
         s_red[2][w] = c2;
+        s_red[3][w] = c3;
     }
     __syncthreads();
     if (tid == 0) {
-        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
         for (int i = 0; i < HQ_WG / 64; ++i) {
             d0 += s_red[0][i];
             d1 += s_red[1][i];
             d2 = fmax(d2, s_red[2][i]);
+            d3 = fmax(d3, s_red[3][i]);
         }
         out[0] = d0;
         out[1] = d1;
         out[2] = d2;
+        out[3] = d3;
     }
 }
 
@@ -177,6 +186,7 @@ __device__ __forceinline__ WaveIter wave_iter(uint32_t groups) {
 // Scalars of one layer update, fixed for the whole layer.
 struct ModeScalars {
     double alpha, beta;       // coefficients of U~ and D~ in (12)
+    double alpha0;            // mu^{k-1}(n) / lambda^k(n-1): first inner step (literal form)
     double pdn, pself, pup;   // p(n-1), p(n), p(n+1) (residual)
     double is_dn, is_up;      // inverse storage scales of layers n-1, n+1
     double s_self, is_self;   // storage scale of layer n and its inverse
@@ -194,9 +204,10 @@ __device__ __forceinline__ ModeScalars mode_scalars(const SweepParams& P, int n,
     ms.is_self = P.inv_scale[n];
     if (MODE == M_PASS1 || MODE == M_WRITE) {
         ms.beta = lam[n] / mu[n + 1];  // lambda^{k-1}(n) / mu^{k-1}(n+1)
+        ms.alpha0 = mu[n] / lam[n - 1];  // mu^{k-1}(n) / lambda^k(n-1)
         if (MODE == M_WRITE)
-            ms.alpha = inner_one ? mu[n] / lam[n - 1]  // mu^{k-1}(n) / lambda^k(n-1)
-                                 : alpha_closed[n];    // closed-form limit (first pass)
+            ms.alpha = inner_one == 1 ? ms.alpha0        // one inner update
+                                      : alpha_closed[n];  // from the first pass (closed or literal)
     } else {
         ms.pdn = (n >= 1) ? pn[n - 1] : 0.0;
         ms.pself = pn[n];
@@ -316,7 +327,8 @@ template <typename T, int MODE, bool TRACK_DELTA, bool STORED, int BF = 0, int H
 __device__ __forceinline__ void segment_compute(const SweepParams& P, const LayerArgs& A, T* __restrict__ x,
                                                 const SegScal& sc, const SegVec& r, const uint16_t* s_rank,
                                                 const uint16_t* s_unrank, const uint32_t* s_qstart,
-                                                const ModeScalars& ms, double& acc0, double& acc1, double& acc2) {
+                                                const ModeScalars& ms, double& acc0, double& acc1, double& acc2,
+                                                double& acc3) {
     constexpr int MAXB = BF ? BF : HQ_MAXB, MAXH = HF ? HF : HQ_MAXH;
     const int lane = threadIdx.x & 63;
     const int n = A.n, N = P.N;
@@ -388,8 +400,18 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
             const double inv = 1.0 / (P.Lam + mu_m);
             const double Ut = U * inv, Dt = D * inv;
             if (MODE == M_PASS1) {
-                acc0 += Ut;
-                acc1 += mu_m * Dt;
+                if (TRACK_DELTA) {
+                    // literal inner loop: sum mu U~, sum mu D~, max U~ and the
+                    // first step's change against the previous iterate
+                    acc0 += mu_m * Ut;
+                    acc1 += mu_m * Dt;
+                    acc2 = fmax(acc2, Ut);
+                    const double v0 = ms.alpha0 * Ut + beta * Dt;
+                    acc3 = fmax(acc3, fabs(v0 - (double)x[offSelf + t] * is_self));
+                } else {
+                    acc0 += Ut;
+                    acc1 += mu_m * Dt;
+                }
             } else {
                 const double p = alpha * Ut + beta * Dt;
                 const uint32_t o = offSelf + t;
@@ -412,7 +434,9 @@ __device__ __forceinline__ void segment_update(const SweepParams& P, const Layer
                                                double& acc1, double& acc2) {
     const SegScal sc = fetch_scal(P, A, si);
     const SegVec r = fetch_vec(P, P.b, P.H, sc, STORED);
-    segment_compute<T, MODE, TRACK_DELTA, STORED>(P, A, x, sc, r, s_rank, s_unrank, s_qstart, ms, acc0, acc1, acc2);
+    double unused = 0.0;
+    segment_compute<T, MODE, TRACK_DELTA, STORED>(P, A, x, sc, r, s_rank, s_unrank, s_qstart, ms, acc0, acc1, acc2,
+                                                  unused);
 }
 
 template <typename T, int MODE, bool TRACK_DELTA, bool STORED, int BF = 0, int HF = 0>
@@ -431,7 +455,7 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
     if (tid <= b + 1) s_qstart[tid] = P.lo_qstart[tid];
     __syncthreads();
     const ModeScalars ms = mode_scalars<MODE>(P, A.n, inner_one, P.sc.lam, P.sc.mu, P.sc.alpha, P.sc.pn);
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     // Software pipeline over this wave's segments: the scalar record of
     // segment i+2 and the lane-parallel record of segment i+1 are in flight
     // while segment i is processed.
@@ -449,24 +473,42 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
         if (si + it.step < it.end) v1 = fetch_vec(P, b, H, s1, STORED);
         if (si + 2 * it.step < it.end) s2 = fetch_scal(P, A, si + 2 * it.step);
         segment_compute<T, MODE, TRACK_DELTA, STORED, BF, HF>(P, A, x, s0, v0, s_rank, s_unrank, s_qstart, ms, acc0,
-                                                              acc1, acc2);
+                                                              acc1, acc2, acc3);
         s0 = s1;
         v0 = v1;
         s1 = s2;
     }
-    block_partial3(acc0, acc1, acc2, P.partials);
+    block_partial(acc0, acc1, acc2, acc3, P.partials);
 }
 
 // Layer scalars from the work-group partials of the kernel just run on the
 // same stream (one work-group, fixed summation order).
+// inner: 0 closed form, 1 one update, 2 literal loop with tolerance P.delta.
 __global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode, int n, uint32_t count,
                                                          int inner_one) {
-    double tot[3];
-    sum_partials3(P.partials, count, tot);
+    double tot[4];
+    sum_partials(P.partials, count, tot);
     if (threadIdx.x != 0) return;
     double* misc = P.sc.misc;
     const int N = P.N;
-    if (mode == M_PASS1) {
+    if (mode == M_PASS1 && inner_one == 2) {
+        // the inner loop of Algorithm 1 as written: p^r = (mu_r / L) U~ +
+        // beta D~ with mu_0 = mu^{k-1}(n) and mu_{r+1} = sum mu_m p^r; it
+        // stops at the first step whose max change is <= delta.  The first
+        // change (against the previous iterate) came from the pass; after
+        // that p^{r+1} - p^r = ((mu_{r+1} - mu_r) / L) U~.
+        const double L = P.sc.lam[n - 1], beta = P.sc.lam[n] / P.sc.mu[n + 1];
+        const double s_muU = tot[0], s_muD = tot[1], maxU = tot[2];
+        double mu_r = P.sc.mu[n], change = tot[3];
+        for (int r = 0; r < 1000000 && !(change <= P.delta); ++r) {
+            const double mu_next = (mu_r / L) * s_muU + beta * s_muD;
+            change = fabs(mu_next - mu_r) / L * maxU;
+            mu_r = mu_next;
+        }
+        const double a = mu_r / L;
+        if (!isfinite(a)) misc[2] = 1.0;
+        P.sc.alpha[n] = a;
+    } else if (mode == M_PASS1) {
         // mu* = B / (1 - A) with A = sum mu U~ / lambda(n-1) = 1 - Lambda S_U / lambda(n-1)
         // (since sum (Lambda + mu_m) U~ = lambda(n-1)), so alpha = mu*/lambda(n-1)
         // = beta S_muD / (Lambda S_U).
@@ -475,7 +517,7 @@ __global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode
         if (!(tot[0] > 0.0) || !isfinite(a)) misc[2] = 1.0;
         P.sc.alpha[n] = a;
     } else if (mode == M_WRITE) {
-        const double used = inner_one ? P.sc.mu[n] / P.sc.lam[n - 1] : P.sc.alpha[n];
+        const double used = inner_one == 1 ? P.sc.mu[n] / P.sc.lam[n - 1] : P.sc.alpha[n];
         const double lam = P.Lam * tot[0], mu = tot[1];
         if (!isfinite(lam) || !(mu > 0.0) || !isfinite(mu)) misc[2] = 1.0;
         P.sc.lam[n] = lam;
@@ -595,7 +637,7 @@ __global__ __launch_bounds__(HQ_WG) void init_kernel(SweepParams P, LayerArgs A,
     const WaveIter it = wave_iter(A.groups);
     for (uint32_t si = it.begin; si < it.end; si += it.step)
         init_segment<T>(P, A, x, si, A.init_mode, xu, given, orig_bit, acc0, acc1);
-    block_partial3(acc0, acc1, 0.0, P.partials);
+    block_partial(acc0, acc1, 0.0, 0.0, P.partials);
 }
 
 // Birth-death marginal p(n), n = 0..N, of (10) from lambda(n), mu(n), with
@@ -1089,7 +1131,9 @@ static void launch_layer_s(int mode, bool track_delta, const SweepParams& P, con
                            int inner_one, hipStream_t s) {
     dim3 grid(grid_for(A.groups)), block(HQ_WG);
     if (!track_delta && launch_layer_fixed<T>(mode, STORED, P, A, x, inner_one, s)) return;
-    if (mode == M_PASS1)
+    if (mode == M_PASS1 && track_delta)
+        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, true, STORED>), grid, block, 0, s, P, A, x, inner_one);
+    else if (mode == M_PASS1)
         hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
     else if (mode == M_WRITE && track_delta)
         hipLaunchKernelGGL((layer_kernel<T, M_WRITE, true, STORED>), grid, block, 0, s, P, A, x, inner_one);

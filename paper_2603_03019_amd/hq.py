@@ -20,7 +20,7 @@ HQ_MAX_N = 30
 HQ_OK, HQ_ERR_INVALID_ARG, HQ_ERR_OUT_OF_MEMORY, HQ_ERR_DEVICE, HQ_ERR_NOT_CONVERGED, HQ_ERR_NUMERIC, \
     HQ_ERR_STATE = range(7)
 HQ_FP64, HQ_FP32, HQ_FP32_POLISH64 = 0, 1, 2
-HQ_INNER_CLOSED, HQ_INNER_ONE = 0, 1
+HQ_INNER_CLOSED, HQ_INNER_ONE, HQ_INNER_LITERAL = 0, 1, 2
 HQ_INIT_UNIFORM, HQ_INIT_PRODUCT, HQ_INIT_STATE, HQ_INIT_LEARNED = 0, 1, 2, 3
 HQ_STOP_RESIDUAL, HQ_STOP_DELTA = 0, 1
 HQ_BUFFER_UNLIMITED, HQ_BUFFER_MAX = -1, 65536
@@ -51,7 +51,7 @@ class hq_options(ctypes.Structure):
                 ("tile_bits", ctypes.c_int), ("device", ctypes.c_int), ("stored_layers", ctypes.c_int),
                 ("init_rho", ctypes.POINTER(ctypes.c_double)),
                 ("init_state", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
-                ("mlp", ctypes.c_void_p), ("buffer", ctypes.c_int)]
+                ("mlp", ctypes.c_void_p), ("buffer", ctypes.c_int), ("delta", ctypes.c_double)]
 
 
 class hq_info(ctypes.Structure):

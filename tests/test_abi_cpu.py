@@ -45,7 +45,7 @@ def _ok_args(N=4, J=3):
 @pytest.mark.parametrize("case", ["N0", "Nbig", "J0", "neg_lambda", "nan_lambda", "zero_mu", "inf_mu",
                                   "not_perm", "out_of_range", "bad_precision", "bad_inner", "product_no_rho",
                                   "state_no_state", "bad_rho", "bad_tile", "bad_buffer", "big_buffer",
-                                  "unstable_room"])
+                                  "unstable_room", "literal_no_delta"])
 def test_invalid_arguments_rejected_on_host(case):
     N, J, lam, mu, pref = _ok_args()
     kw = {}
@@ -95,6 +95,8 @@ def test_invalid_arguments_rejected_on_host(case):
         kw["buffer"] = -2
     elif case == "big_buffer":
         kw["buffer"] = hq.HQ_BUFFER_MAX + 1
+    elif case == "literal_no_delta":
+        kw["inner"] = hq.HQ_INNER_LITERAL
     elif case == "unstable_room":
         kw["buffer"] = hq.HQ_BUFFER_UNLIMITED
         lam = lam * (4.0 / lam.sum())  # Lambda = sum of the service rates

@@ -50,21 +50,25 @@ def test_small_fp64_converged_matches_oracle_and_dense(idx):
     assert abs(info["iterations"] - ref.iterations) <= 1
 
 
-@pytest.mark.parametrize("inner", ["closed", "one"])
+INNER = {"closed": hq.HQ_INNER_CLOSED, "one": hq.HQ_INNER_ONE, "literal": hq.HQ_INNER_LITERAL}
+
+
+@pytest.mark.parametrize("inner", ["closed", "one", "literal"])
 @pytest.mark.parametrize("N,J,b,cfg", [(10, 40, 0, 1), (12, 60, 4, 2), (14, 120, 6, 3), (15, 90, 10, 2),
                                        (13, 50, 12, 2), (16, 200, 8, 3)])
 def test_iteration_path_matches_oracle(N, J, b, cfg, inner):
     """Same iterate after k outer iterations (Gauss-Seidel across layers,
-    the same inner reading), entry by entry, for several tile widths."""
+    the same inner reading), entry by entry, for several tile widths.  The
+    literal inner loop uses delta = 1e-6, where it takes a few inner steps."""
     inst = config_instance(cfg, 11, N=N, J=J)
     say(f"case path N={N} J={J} b={b} inner={inner}")
-    ctx = _gpu(inst, inner=hq.HQ_INNER_ONE if inner == "one" else hq.HQ_INNER_CLOSED, tile_bits=b)
+    ctx = _gpu(inst, inner=INNER[inner], tile_bits=b, delta=1e-6)
     done = 0
     for k in (1, 2, 5):
         hq.hq_iterate(ctx, k - done)
         done = k
         got = hq.hq_conditional(ctx)
-        ref = cpu.solve(inst, tol=0.0, max_iters=k, inner=inner)
+        ref = cpu.solve(inst, tol=0.0, max_iters=k, inner=inner, delta=1e-6)
         assert _rel_close(got, ref.pcond, 1e-11) == 0, f"k={k}"
         sc = hq.hq_layer_scalars(ctx)
         np.testing.assert_allclose(sc[:, 0], ref.lam_n, rtol=1e-12)
@@ -216,3 +220,16 @@ def test_stored_coefficient_layers(stored):
     ref = cpu.solve(inst, tol=0.0, max_iters=4, inner="one")
     assert _rel_close(hq.hq_conditional(ctx), ref.pcond, 1e-11) == 0
     assert hq.hq_residual(ctx) == pytest.approx(cpu.residual(inst, ref.P), rel=1e-9)
+
+
+def test_literal_inner_loop_converges_to_the_same_law():
+    # any inner tolerance keeps the fixed point (the stationary law)
+    inst = config_instance(2, 12, N=14, J=100)
+    say("case literal inner converged")
+    ref = cpu.solve(inst, tol=1e-13)
+    for delta in (1e-3, 1e-9):
+        ctx = _gpu(inst, inner=hq.HQ_INNER_LITERAL, delta=delta)
+        hq.hq_solve(ctx, 1e-12)
+        assert np.abs(hq.hq_state(ctx) - ref.P).sum() <= 1e-10
+    with pytest.raises(hq.HQError):
+        hq.hq_solve_batch([_gpu(inst, inner=hq.HQ_INNER_LITERAL, delta=1e-6)], 1e-8)
