@@ -213,6 +213,45 @@ def fp32_leg(hq, inst, tol: float, P64, steps: int):
     }
 
 
+def inner_leg(hq, inst, tol: float):
+    """Outer iterations and time to tol for the readings of the inner loop:
+    one update, the closed-form limit, and the literal loop at two
+    tolerances (the same instance and stopping rule)."""
+    import torch
+
+    out = {}
+    for name, kw in (("one", dict(inner=hq.HQ_INNER_ONE)), ("closed", dict(inner=hq.HQ_INNER_CLOSED)),
+                     ("literal_1e-6", dict(inner=hq.HQ_INNER_LITERAL, delta=1e-6)),
+                     ("literal_1e-10", dict(inner=hq.HQ_INNER_LITERAL, delta=1e-10))):
+        ctx = hq.create_from_instance(inst, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = hq.hq_solve(ctx, tol)
+        out[name] = {"iterations": info["iterations"], "time_to_tol_s": time.perf_counter() - t,
+                     "sweep_ms_per_iteration": 1e3 * info["sweep_seconds"] / max(info["iterations"], 1)}
+        hq.hq_destroy(ctx)
+    return out
+
+
+def dispatch_leg(hq, ctx, inst):
+    """Dispatch probabilities and mean travel time of the solved instance
+    (superset-sum transform of P); synthetic travel times."""
+    import numpy as np
+    import torch
+
+    d = np.linalg.norm(inst.atom_xy[:, None, :] - inst.unit_xy[None, :, :], axis=2)
+    travel = 0.03 + d / 0.5
+    hq.hq_dispatch(ctx, travel)  # first call allocates the transform buffer
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    q, mt = hq.hq_dispatch(ctx, travel)
+    dt = time.perf_counter() - t
+    rho, _ = hq.hq_marginals(ctx)
+    return {"seconds": dt, "mean_travel": mt,
+            "max_flow_gap": float(np.abs((inst.lam[:, None] * q).sum(axis=0) - inst.nu * rho).max()),
+            "note": "P export + 6 superset-sum passes over 2^26 doubles + per-node gather"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,8 +359,12 @@ def main():
     }
     if not args.no_legs and args.precision == "fp64":
         plain_s, plain_iters = wall / args.steps, iters / args.steps
+        print("bench: dispatch measures", flush=True)
+        out["dispatch"] = dispatch_leg(hq, ctx, inst)
         P64 = hq.hq_state(ctx)
         hq.hq_destroy(ctx)
+        print("bench: inner-loop readings", flush=True)
+        out["inner_forms"] = inner_leg(hq, inst, args.tol)
         print("bench: fp32 form", flush=True)
         out["fp32_form"] = fp32_leg(hq, inst, args.tol, P64, 1)
         del P64
