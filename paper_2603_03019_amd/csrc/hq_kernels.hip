@@ -1099,24 +1099,32 @@ static uint32_t grid_for(uint32_t groups) {
 // stored coefficients) and the residual.  Other shapes and modes use the
 // run-time-shaped kernels.
 template <typename T, int BF, int HF>
-static void launch_fixed(int mode, bool stored, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
-                         hipStream_t s) {
+static void launch_fixed(int mode, bool stored, bool track, const SweepParams& P, const LayerArgs& A, T* x,
+                         int inner_one, hipStream_t s) {
     dim3 grid(grid_for(A.groups)), block(HQ_WG);
     if (mode == M_WRITE && stored)
         hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, true, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
     else if (mode == M_WRITE)
         hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+    else if (mode == M_PASS1 && track)
+        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, true, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+    else if (mode == M_PASS1)
+        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
     else
         hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
 }
 
+// The sweep (computed or stored coefficients, without the delta tracking of
+// the paper's stopping rule), the first pass of the closed and literal inner
+// forms and the residual, for computed coefficients.
 template <typename T>
-static bool launch_layer_fixed(int mode, bool stored, const SweepParams& P, const LayerArgs& A, T* x,
-                               int inner_one, hipStream_t s) {
-    if (mode != M_WRITE && (mode != M_RESID || stored)) return false;
+static bool launch_layer_fixed(int mode, bool stored, bool track, const SweepParams& P, const LayerArgs& A,
+                               T* x, int inner_one, hipStream_t s) {
+    if (mode == M_WRITE && track) return false;
+    if (mode != M_WRITE && stored) return false;
 #define HQ_FIXED(BV, HV)                                                   \
     if (P.b == BV && P.H == HV) {                                          \
-        launch_fixed<T, BV, HV>(mode, stored, P, A, x, inner_one, s);      \
+        launch_fixed<T, BV, HV>(mode, stored, track, P, A, x, inner_one, s); \
         return true;                                                       \
     }
     HQ_FIXED(10, 6) HQ_FIXED(10, 7) HQ_FIXED(10, 8) HQ_FIXED(10, 9) HQ_FIXED(10, 10) HQ_FIXED(10, 11)
@@ -1130,7 +1138,7 @@ template <typename T, bool STORED>
 static void launch_layer_s(int mode, bool track_delta, const SweepParams& P, const LayerArgs& A, T* x,
                            int inner_one, hipStream_t s) {
     dim3 grid(grid_for(A.groups)), block(HQ_WG);
-    if (!track_delta && launch_layer_fixed<T>(mode, STORED, P, A, x, inner_one, s)) return;
+    if (launch_layer_fixed<T>(mode, STORED, track_delta, P, A, x, inner_one, s)) return;
     if (mode == M_PASS1 && track_delta)
         hipLaunchKernelGGL((layer_kernel<T, M_PASS1, true, STORED>), grid, block, 0, s, P, A, x, inner_one);
     else if (mode == M_PASS1)
