@@ -354,13 +354,18 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
         const uint32_t m = Tabs | L;
         // every neighbour value first: low units in the small segments
         // (T, q -+ 1), high units segment-aligned and coalesced
-        double vl[MAXB], vh[MAXH];
+        // with a run-time shape the high units go in chunks of HQ_HCHUNK
+        // (a bounded register budget); with a fixed shape all at once
+        constexpr int HB = HF ? MAXH : HQ_HCHUNK;
+        double vl[MAXB], vh[HB];
 #pragma unroll
         for (int l = 0; l < MAXB; ++l)
             if (l < b) vl[l] = (double)x[hqlayout::low_neighbour(L, l, offDlo, offUlo, s_rank)];
+        if (HF) {
 #pragma unroll
-        for (int k = 0; k < MAXH; ++k)
-            if (k < H) vh[k] = (double)x[bcast(r.seg, (uint32_t)k) + t];
+            for (int k = 0; k < HB; ++k)
+                if (k < H) vh[k] = (double)x[bcast(r.seg, (uint32_t)k) + t];
+        }
         double U = 0.0, D = 0.0, mu_lo = 0.0;
 #pragma unroll
         for (int l = 0; l < MAXB; ++l) {
@@ -375,14 +380,34 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
                 }
             }
         }
+        if (HF) {
 #pragma unroll
-        for (int k = 0; k < MAXH; ++k) {
-            if (k < H) {
-                if ((Tb >> k) & 1u) {
-                    const double c = STORED ? cs[(size_t)(b + k) * A.count + t] : unit_coef(P, sc, r, b + k, L);
-                    U += c * vh[k];
-                } else {
-                    D += nuc[b + k] * vh[k];
+            for (int k = 0; k < HB; ++k) {
+                if (k < H) {
+                    if ((Tb >> k) & 1u) {
+                        const double c = STORED ? cs[(size_t)(b + k) * A.count + t] : unit_coef(P, sc, r, b + k, L);
+                        U += c * vh[k];
+                    } else {
+                        D += nuc[b + k] * vh[k];
+                    }
+                }
+            }
+        } else {
+            for (int k0 = 0; k0 < H; k0 += HB) {
+#pragma unroll
+                for (int j = 0; j < HB; ++j)
+                    if (k0 + j < H) vh[j] = (double)x[bcast(r.seg, (uint32_t)(k0 + j)) + t];
+#pragma unroll
+                for (int j = 0; j < HB; ++j) {
+                    const int k = k0 + j;
+                    if (k < H) {
+                        if ((Tb >> k) & 1u) {
+                            const double c = STORED ? cs[(size_t)(b + k) * A.count + t] : unit_coef(P, sc, r, b + k, L);
+                            U += c * vh[j];
+                        } else {
+                            D += nuc[b + k] * vh[j];
+                        }
+                    }
                 }
             }
         }
