@@ -27,16 +27,20 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def big():
-    inst = config_instance(3, 0)  # the benchmark workload
-    assert inst.N == 26 and inst.J == 1000
+def _tables(inst):
     m = np.arange(1 << inst.N, dtype=np.uint32)
     pop = np.bitwise_count(m)
     mu_m = np.zeros(1 << inst.N)
     for u in range(inst.N):
         mu_m += inst.nu[u] * ((m >> u) & 1)
-    return inst, pop, mu_m
+    return pop, mu_m
+
+
+@pytest.fixture(scope="module")
+def big():
+    inst = config_instance(3, 0)  # the benchmark workload
+    assert inst.N == 26 and inst.J == 1000
+    return (inst, *_tables(inst))
 
 
 def _sample_layer(rng, N, n, k):
@@ -48,9 +52,21 @@ def _sample_layer(rng, N, n, k):
 
 
 def test_full_size_layer_update(big):
-    inst, pop, mu_m = big
+    _layer_update_parity(*big)
+
+
+@pytest.mark.parametrize("N", [27, 28])
+def test_larger_tile_shapes_layer_update(N):
+    # N = 27 runs the b = 10, H = 17 kernels and N = 28 the b = 12, H = 16
+    # ones (the tile width grows to 12 bits from N = 28)
+    inst = config_instance(3, 0, N=N)
+    say(f"case N={N} tables")
+    _layer_update_parity(inst, *_tables(inst))
+
+
+def _layer_update_parity(inst, pop, mu_m):
     N, Lam = inst.N, inst.Lambda
-    say("case N=26 layer update: iterate")
+    say(f"case N={N} layer update: iterate")
     ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE)
     hq.hq_iterate(ctx, 2)
     S1 = hq.hq_conditional(ctx)
@@ -64,8 +80,8 @@ def test_full_size_layer_update(big):
     def mu_of(S, n):
         return float((mu_m[pop == n] * S[pop == n]).sum())
 
-    for n in (1, 3, 9, 13, 17, 20, 24, 25):
-        say(f"case N=26 layer {n}")
+    for n in (1, 3, 9, N // 2, N - 9, N - 6, N - 2, N - 1):
+        say(f"case N={N} layer {n}")
         alpha = mu_of(S1, n) / lam_of(S2, n - 1)  # mu^2(n) / lambda^3(n-1)
         beta = lam_of(S1, n) / mu_of(S1, n + 1)   # lambda^2(n) / mu^2(n+1)
         states = _sample_layer(rng, N, n, 1500)
