@@ -134,7 +134,7 @@ void hq_default_options(hq_options* opts);
  *              most preferred first; each row must be a permutation
  *   opts       nullable; NULL = defaults
  *   out        receives the context (NULL on failure)
- * Preprocessing (unit relabelling, preference trie, per-tile dispatch
+ * Preprocessing (unit relabelling, merged dispatch terms, per-tile dispatch
  * tables) and device allocation happen here.  Errors: HQ_ERR_INVALID_ARG,
  * HQ_ERR_OUT_OF_MEMORY, HQ_ERR_DEVICE.
  */

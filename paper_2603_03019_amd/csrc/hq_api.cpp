@@ -538,9 +538,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->layers[n] = A;
     }
     c->max_groups = max_groups;
-    // Layers near the top (nearly all units busy) have long per-lane walks;
-    // their coefficients are computed once and stored (unit-major).  Auto:
-    // the top layers while they hold at most 2^N / 32 states.
+    // Layers near the top (nearly all units busy) have the longest per-tile
+    // programs; their coefficients are computed once and stored
+    // (unit-major).  Auto: the top layers while they hold at most 2^N / 32
+    // states.
     int top = o.stored_layers;
     if (top == 0) {
         uint64_t acc = 0;

@@ -10,7 +10,7 @@
 #define HQ_WG 256           // threads per work-group of the layer kernels
 #define HQ_NPART 4          // partials per work-group of the layer kernels (sum, sum, max, max)
 #ifndef HQ_HCHUNK
-#define HQ_HCHUNK 8         // independent high-unit neighbour loads issued together
+#define HQ_HCHUNK 8         // high-unit neighbour loads issued together by the run-time-shape sweep
 #endif
 #define HQ_GRID 2048        // persistent work-groups per layer launch (8 per CU)
 

@@ -157,15 +157,18 @@ __device__ void sum_partials(const double* partials, uint32_t count, double out[
 
 // ---------------------------------------------------------------------------
 // The layer kernel.  MODE:
-//   M_PASS1  closed inner form, first pass: reduce S_U = sum U~(m) and
-//            S_muD = sum mu_m D~(m) over the layer, then alpha_n.
+//   M_PASS1  first pass of the closed and literal inner forms: reduce
+//            S_U = sum U~(m) (closed) or sum mu_m U~(m) (literal, with
+//            TRACK_DELTA: also max U~ and the first step's change) and
+//            S_muD = sum mu_m D~(m) over the layer; the finalize step then
+//            derives alpha_n.
 //   M_WRITE  update (12): p_n(m) = alpha_n U~(m) + beta_n D~(m), write it,
 //            reduce lambda(n) = Lambda sum p_n and mu(n) = sum mu_m p_n.
 //   M_RESID  balance residual of (1) for the states of layer n.
 // with U~(m) = sum_{u in m} a(m,u) p_{n-1}(m\u) / (Lambda + mu_m) and
 //      D~(m) = sum_{u notin m} nu_u p_{n+1}(m+u) / (Lambda + mu_m).
 // STORED: the layer's coefficients a(m, u) are read from `coefs` instead
-// of being evaluated from the per-tile tables and the trie.
+// of being evaluated from the per-tile uniform coefficients and programs.
 // ---------------------------------------------------------------------------
 // Wave-granular segment iteration for the layer kernels: each 64-lane wave
 // owns one segment at a time and walks its own share of the segment list,
@@ -565,7 +568,7 @@ __global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode
 // (coefs[coef_base + u * count + rank]), by the plain trie walk of
 // Algorithm 3's rule: a node credits its rate to its unit iff every unit on
 // its path (itself included) is busy in m.  Run once per instance for the
-// layers whose on-the-fly walk would be long (nearly full states).
+// top layers (nearly full states), where the per-tile programs are longest.
 __global__ __launch_bounds__(HQ_WG) void coef_kernel(SweepParams P, LayerArgs A, double* __restrict__ coefs,
                                                      uint32_t nnodes) {
     const int tid = threadIdx.x;
