@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hq_tables.h"  // ProgTerm
+
 #define HQ_MAXB 12          // largest low-bit tile width b
 #define HQ_MAXH 26          // largest high-bit count H = N - b
 #define HQ_WG 256           // threads per work-group of the layer kernels
@@ -13,16 +15,6 @@
 #define HQ_HCHUNK 8         // high-unit neighbour loads issued together by the run-time-shape sweep
 #endif
 #define HQ_GRID 2048        // persistent work-groups per layer launch (8 per CU)
-
-// One term of a tile's dispatch program: unit u (given by the group the
-// term sits in) gains `rate` in every state of the tile whose low bits
-// contain `mask` (the low units ranked before u by the demand nodes summed
-// into the term).
-struct ProgTerm {
-    uint32_t mask;
-    uint32_t pad;
-    double rate;
-};
 
 // One node of the merged preference trie, in preorder.  A node stands for
 // a preference prefix shared by one or more demand nodes; `rate` is the
