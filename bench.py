@@ -27,19 +27,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 L1 residual & state-updates/s at N=26; warm/batched vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2603_03019_amd", "csrc", "hq_kernels.hip")
+# sources that decide what the sweep launches do: the kernels, and the host
+# code that builds the dispatch programs and picks the stored layers
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_03019_amd", "csrc", f)
+               for f in ("hq_kernels.hip", "hq_api.cpp", "hq_tables.h", "hq_layout.h")]
 
 
 def kernel_source_hash() -> str:
     import hashlib
 
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(hashlib.sha256(f.read()).digest())
+    return h.hexdigest()
 
 
 def measured_traffic(N: int, precision: str):
     """HBM bytes per outer iteration of the layer kernels, from the committed
-    counter summary; None when the kernel source changed since it was taken."""
+    counter summary; None when the sweep's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"layer_kernel_n{N}_{precision}_hbm_bytes.txt")
     if not os.path.exists(path):
         return None

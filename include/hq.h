@@ -70,7 +70,9 @@ enum {
 /* initial iterate */
 enum {
     HQ_INIT_UNIFORM = 0, /* p_n(m) = 1 / C(N, n), as Algorithm 1 step 2 */
-    HQ_INIT_PRODUCT = 1, /* p_n(m) proportional to prod_{u in m} x_u, x_u = rho_u / (1 - rho_u), from init_rho */
+    HQ_INIT_PRODUCT = 1, /* p_n(m) proportional to prod_{u in m} x_u, with x fitted on the host so that the
+                            start's busy probabilities (layer law from (10) with the start's own mu(n))
+                            equal init_rho; targets no start can meet give the closest one found */
     HQ_INIT_STATE = 2,   /* resume: conditional probabilities p_n(m) from init_state (bitmask order) */
     HQ_INIT_LEARNED = 3  /* product form with rho predicted by opts.mlp (falls back to uniform) */
 };
@@ -91,8 +93,10 @@ typedef struct {
     int tile_bits;            /* low bits per tile b (4..12); <= 0: choose */
     int device;               /* HIP device ordinal; < 0: current device */
     int stored_layers;        /* top layers whose dispatch coefficients are precomputed and
-                                 stored (FP64, N values per state): 0 = choose (at most
-                                 2^N/32 states), < 0 = none, k > 0 = layers N-k..N-1 */
+                                 stored (FP64, N values per state): 0 = choose (from the top
+                                 down, the layers whose per-tile dispatch programs average
+                                 >= 32 terms per state, within 4 GiB), < 0 = none,
+                                 k > 0 = layers N-k..N-1 */
     const double* init_rho;   /* [N] per-unit utilisations for HQ_INIT_PRODUCT (copied) */
     const double* init_state; /* [2^N] conditional probabilities for HQ_INIT_STATE (copied) */
     void* stream;             /* hipStream_t to run on (e.g. torch's current stream); NULL = own stream */

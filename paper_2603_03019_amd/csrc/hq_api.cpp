@@ -19,6 +19,7 @@
 
 #include "hq.h"
 #include "hq_internal.h"
+#include "hq_init.h"
 #include "hq_layout.h"
 
 namespace hqk {
@@ -39,6 +40,10 @@ hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, 
 hipError_t launch_batch(bool fp32, int block, const BatchItem* items, BatchOut* outs, int count,
                         unsigned int* next, int grid, hipStream_t s);
 }  // namespace hqk
+
+// automatic choice of stored-coefficient layers (see hq_create)
+#define HQ_STORE_TERMS 32.0
+#define HQ_STORE_BYTES (4ull << 30)
 
 namespace {
 
@@ -99,6 +104,7 @@ struct hq_ctx {
     bool lam_zero = false;
     hq_options opts{};
     std::vector<double> rho_init;    // relabelled
+    std::vector<double> x_init;      // product-form weights calibrated to rho_init
     std::vector<double> state_init;  // original bitmask order
     std::vector<int> orig;           // new label -> original unit
     std::vector<double> nu;          // relabelled service rates
@@ -343,6 +349,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->learned = true;
     }
     c->opts.mlp = nullptr;
+    if (!c->rho_init.empty()) {
+        c->x_init.resize(N);
+        hqinit::calibrate(N, c->rho_init.data(), c->nu.data(), Lam, o.buffer, c->x_init.data());
+    }
     if (o.init == HQ_INIT_STATE) c->state_init.assign(o.init_state, o.init_state + (1ull << N));
     c->opts.init_rho = nullptr;
     c->opts.init_state = nullptr;
@@ -391,16 +401,30 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     }
     c->max_groups = max_groups;
     // Layers near the top (nearly all units busy) have the longest per-tile
-    // programs; their coefficients are computed once and stored
-    // (unit-major).  Auto: the top layers while they hold at most 2^N / 32
-    // states.
+    // programs; their coefficients can be computed once and stored
+    // (unit-major, N doubles per state).  Auto: from layer N-1 down, every
+    // layer whose tiles average at least HQ_STORE_TERMS program terms per
+    // state, within HQ_STORE_BYTES of coefficients.  Reading N stored
+    // values per state costs about as much as ~100 program terms; below
+    // ~20 terms storing is measurably slower.
     int top = o.stored_layers;
     if (top == 0) {
-        uint64_t acc = 0;
-        top = 0;
+        std::vector<double> num(N + 1, 0.0), den(N + 1, 0.0);
+        const uint64_t ntiles = 1ull << (N - b);
+        for (uint64_t T = 0; T < ntiles; ++T) {
+            const double len = (double)(prog_off[T * (N + 1) + N] - prog_off[T * (N + 1)]);
+            const int h = __builtin_popcountll(T);
+            for (int q = 0; q <= b; ++q) {
+                const double w = binom_d(b, q);
+                num[h + q] += w * len;
+                den[h + q] += w;
+            }
+        }
+        uint64_t bytes = 0;
         for (int n = N - 1; n >= 1; --n) {
-            acc += (uint64_t)binom_d(N, n);
-            if (acc > (1ull << N) / 32) break;
+            const uint64_t add = (uint64_t)N * (uint64_t)binom_d(N, n) * sizeof(double);
+            if (num[n] < HQ_STORE_TERMS * den[n] || bytes + add > HQ_STORE_BYTES) break;
+            bytes += add;
             ++top;
         }
     } else if (top < 0) {
@@ -505,23 +529,17 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
 // iteration
 // ----------------------------------------------------------------------------
 
-// Host part of the initial iterate: product-form weights x_u = rho/(1-rho)
-// (uploaded) and the elementary symmetric polynomials e_n(x) in FP64.
+// Host part of the initial iterate: the product-form weights calibrated at
+// create time (uploaded) and the elementary symmetric polynomials e_n(x) in
+// FP64.
 // Returns the init mode of the kernels (0 uniform, 1 product, 2 given).
 int prepare_init(hq_ctx* c, std::vector<double>& e) {
     const int N = c->N;
     e.assign(N + 1, 0.0);
     if (c->opts.init == HQ_INIT_PRODUCT) {
-        std::vector<double> xu(N);
-        for (int u = 0; u < N; ++u) {
-            double r = std::min(std::max(c->rho_init[u], 1e-6), 1.0 - 1e-6);
-            xu[u] = r / (1.0 - r);
-        }
-        e[0] = 1.0;
-        for (int u = 0; u < N; ++u)
-            for (int n = u + 1; n >= 1; --n) e[n] += xu[u] * e[n - 1];
+        const std::vector<double>& xu = c->x_init;
+        hqinit::elementary(xu.data(), N, e.data());
         HQ_HIP(hipMemcpyAsync(c->d_xu, xu.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HQ_HIP(hipStreamSynchronize(c->stream));  // xu lives on the stack of this call
         return 1;
     }
     return c->opts.init == HQ_INIT_STATE ? 2 : 0;

@@ -234,7 +234,8 @@ __device__ __forceinline__ double bcast(double v, uint32_t i) {
 }
 
 // The first 64 program terms of a tile are held in registers (lane i holds
-// term i), the rest are read as scalar loads.
+// term i), the rest are read as scalar loads, four terms per batch (the
+// program array ends in inert padding terms, so a batch never leaves it).
 #define HQ_PROG_REG 64
 
 // Wave-uniform part of a segment's record: descriptor and the position of
@@ -297,22 +298,33 @@ __device__ __forceinline__ SegVec fetch_vec(const SweepParams& P, int b, int H, 
 
 // Arrival coefficient of busy unit u for the lane's low pattern L: the
 // tile-uniform part plus the unit's program terms whose mask lies in L.
+// A term applies iff its mask has no bit outside L; the select keeps the
+// sum bit-identical to adding 0.0 for the terms that do not apply.
 __device__ __forceinline__ double unit_coef(const SweepParams& P, const SegScal& sc, const SegVec& r, int u,
                                             uint32_t L) {
     double c = bcast(r.tc, (uint32_t)u);
     const uint32_t i0 = bcast(r.po, (uint32_t)u) - sc.pstart, i1 = bcast(r.po, (uint32_t)u + 1u) - sc.pstart;
-    for (uint32_t i = i0; i < i1; ++i) {
-        uint32_t mk;
-        double rt;
-        if (i < HQ_PROG_REG) {
-            mk = bcast(r.pm, i);
-            rt = bcast(r.pr, i);
-        } else {
-            const HQ_CONST ProgTerm* t = ro(P.prog) + sc.pstart + i;
-            mk = t->mask;
-            rt = t->rate;
+    const uint32_t nL = ~L;
+    const uint32_t ireg = i1 < HQ_PROG_REG ? i1 : HQ_PROG_REG;
+    for (uint32_t i = i0; i < ireg; ++i) {
+        const uint32_t mk = bcast(r.pm, i);
+        const double cn = c + bcast(r.pr, i);
+        c = (nL & mk) == 0u ? cn : c;
+    }
+    const HQ_CONST ProgTerm* tp = ro(P.prog) + sc.pstart;
+    for (uint32_t i = i0 > ireg ? i0 : ireg; i < i1; i += 4) {
+        uint32_t mk4[4];
+        double rt4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            mk4[k] = tp[i + k].mask;
+            rt4[k] = tp[i + k].rate;
         }
-        c += ((L & mk) == mk) ? rt : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double cn = c + rt4[k];
+            c = (i + k < i1 && (nL & mk4[k]) == 0u) ? cn : c;
+        }
     }
     return c;
 }

@@ -154,7 +154,7 @@ inline void build_programs(int N, int b, const std::vector<Term>& terms, std::ve
     }
     size_t total = 0;
     for (auto& v : part) total += v.size();
-    if (total >= 0xffffffffull) throw std::length_error("dispatch program too large");
+    if (total + 3 >= 0xffffffffull) throw std::length_error("dispatch program too large");
     prog.clear();
     prog.reserve(total);
     uint32_t pos = 0;
@@ -170,6 +170,9 @@ inline void build_programs(int N, int b, const std::vector<Term>& terms, std::ve
         prog.insert(prog.end(), part[w].begin(), part[w].end());
         std::vector<ProgTerm>().swap(part[w]);
     }
+    // the sweep reads terms in batches of four; inert terms past the end
+    // keep a batch that starts at the last term inside the array
+    for (int k = 0; k < 3; ++k) prog.push_back(ProgTerm{0xffffffffu, 0u, 0.0});
 }
 
 }  // namespace hqtables

@@ -93,3 +93,28 @@ def test_learned_start_solves_to_the_same_answer():
     cold = hq.hq_solve(hq.create_from_instance(inst), 1e-12)
     say(f"  iterations: exact-rho product start {wi['iterations']} (kept {wi['warm_used']}), cold {cold['iterations']}")
     assert np.abs(hq.hq_state(warm) - ref_r.P).sum() <= 1e-10
+    assert wi["warm_used"] == 1 and wi["iterations"] < cold["iterations"]
+
+
+@pytest.mark.parametrize("C", [0, 3])
+def test_product_start_has_the_target_utilisations(C):
+    # targets that some product-form start meets: those of weights xstar
+    from test_init_check_cpu import start_utilisation
+    inst = config_instance(1, 7, N=9, J=30)
+    rng = np.random.default_rng(5)
+    xstar = np.exp(rng.normal(0.0, 0.7, inst.N))
+    target = start_utilisation(xstar, inst.nu, inst.lam.sum(), C)
+    say(f"case product start C={C}")
+    ctx = hq.create_from_instance(inst, init_rho=target, buffer=C)
+    hq.hq_iterate(ctx, 0)  # the start only
+    rho, _ = hq.hq_marginals(ctx)
+    np.testing.assert_allclose(rho, target, rtol=0, atol=1e-10)
+    # and inside each layer it is the product form of xstar
+    pc = hq.hq_conditional(ctx)
+    m = np.arange(1 << inst.N)
+    bits = ((m[:, None] >> np.arange(inst.N)) & 1).astype(bool)
+    w = np.where(bits, xstar[None, :], 1.0).prod(axis=1)
+    size = bits.sum(axis=1)
+    for n in range(inst.N + 1):
+        sel = size == n
+        np.testing.assert_allclose(pc[sel] / pc[sel].sum(), w[sel] / w[sel].sum(), rtol=1e-9)
