@@ -95,7 +95,8 @@ typedef struct {
     int stored_layers;        /* top layers whose dispatch coefficients are precomputed and
                                  stored (FP64, N values per state): 0 = choose (from the top
                                  down, the layers whose per-tile dispatch programs average
-                                 >= 32 terms per state, within 4 GiB), < 0 = none,
+                                 >= 32 terms per state, within 16 GiB and a quarter
+                                 of the free device memory), < 0 = none,
                                  k > 0 = layers N-k..N-1 */
     const double* init_rho;   /* [N] per-unit utilisations for HQ_INIT_PRODUCT (copied) */
     const double* init_state; /* [2^N] conditional probabilities for HQ_INIT_STATE (copied) */

@@ -43,7 +43,7 @@ hipError_t launch_batch(bool fp32, int block, const BatchItem* items, BatchOut* 
 
 // automatic choice of stored-coefficient layers (see hq_create)
 #define HQ_STORE_TERMS 32.0
-#define HQ_STORE_BYTES (4ull << 30)
+#define HQ_STORE_BYTES (16ull << 30)
 
 namespace {
 
@@ -404,9 +404,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     // programs; their coefficients can be computed once and stored
     // (unit-major, N doubles per state).  Auto: from layer N-1 down, every
     // layer whose tiles average at least HQ_STORE_TERMS program terms per
-    // state, within HQ_STORE_BYTES of coefficients.  Reading N stored
-    // values per state costs about as much as ~100 program terms; below
-    // ~20 terms storing is measurably slower.
+    // state, within HQ_STORE_BYTES of coefficients and a quarter of the
+    // device's free memory.  Reading N stored values per state costs about
+    // as much as evaluating ~30 program terms; below ~20 terms storing is
+    // measurably slower.
     int top = o.stored_layers;
     if (top == 0) {
         std::vector<double> num(N + 1, 0.0), den(N + 1, 0.0);
@@ -420,10 +421,16 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
                 den[h + q] += w;
             }
         }
+        uint64_t budget = HQ_STORE_BYTES;
+        size_t free_b = 0, total_b = 0;
+        if ((o.device < 0 || hipSetDevice(o.device) == hipSuccess) && hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+            budget = std::min<uint64_t>(budget, free_b / 4);
+        else
+            (void)hipGetLastError();
         uint64_t bytes = 0;
         for (int n = N - 1; n >= 1; --n) {
             const uint64_t add = (uint64_t)N * (uint64_t)binom_d(N, n) * sizeof(double);
-            if (num[n] < HQ_STORE_TERMS * den[n] || bytes + add > HQ_STORE_BYTES) break;
+            if (num[n] < HQ_STORE_TERMS * den[n] || bytes + add > budget) break;
             bytes += add;
             ++top;
         }

@@ -372,10 +372,16 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
         // with a run-time shape the high units go in chunks of HQ_HCHUNK
         // (a bounded register budget); with a fixed shape all at once
         constexpr int HB = HF ? MAXH : HQ_HCHUNK;
-        double vl[MAXB], vh[HB];
+        double vl[MAXB], vh[HB], cl[MAXB];
 #pragma unroll
         for (int l = 0; l < MAXB; ++l)
             if (l < b) vl[l] = (double)x[hqlayout::low_neighbour(L, l, offDlo, offUlo, s_rank)];
+        // stored coefficients (zero for idle units): every load issued before any use
+        if (STORED) {
+#pragma unroll
+            for (int l = 0; l < MAXB; ++l)
+                if (l < b) cl[l] = cs[(size_t)l * A.count + t];
+        }
         if (HF) {
 #pragma unroll
             for (int k = 0; k < HB; ++k)
@@ -387,7 +393,7 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
             if (l < b) {
                 const double nl = nuc[l];
                 if ((L >> l) & 1u) {
-                    const double c = STORED ? cs[(size_t)l * A.count + t] : unit_coef(P, sc, r, l, L);
+                    const double c = STORED ? cl[l] : unit_coef(P, sc, r, l, L);
                     U += c * vl[l];
                     mu_lo += nl;
                 } else {
@@ -396,11 +402,17 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
             }
         }
         if (HF) {
+            double ch[HB];
+            if (STORED) {
+#pragma unroll
+                for (int k = 0; k < HB; ++k)
+                    if (k < H && ((Tb >> k) & 1u)) ch[k] = cs[(size_t)(b + k) * A.count + t];
+            }
 #pragma unroll
             for (int k = 0; k < HB; ++k) {
                 if (k < H) {
                     if ((Tb >> k) & 1u) {
-                        const double c = STORED ? cs[(size_t)(b + k) * A.count + t] : unit_coef(P, sc, r, b + k, L);
+                        const double c = STORED ? ch[k] : unit_coef(P, sc, r, b + k, L);
                         U += c * vh[k];
                     } else {
                         D += nuc[b + k] * vh[k];
@@ -412,12 +424,18 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
 #pragma unroll
                 for (int j = 0; j < HB; ++j)
                     if (k0 + j < H) vh[j] = (double)x[bcast(r.seg, (uint32_t)(k0 + j)) + t];
+                double ch[HB];
+                if (STORED) {
+#pragma unroll
+                    for (int j = 0; j < HB; ++j)
+                        if (k0 + j < H && ((Tb >> (k0 + j)) & 1u)) ch[j] = cs[(size_t)(b + k0 + j) * A.count + t];
+                }
 #pragma unroll
                 for (int j = 0; j < HB; ++j) {
                     const int k = k0 + j;
                     if (k < H) {
                         if ((Tb >> k) & 1u) {
-                            const double c = STORED ? cs[(size_t)(b + k) * A.count + t] : unit_coef(P, sc, r, b + k, L);
+                            const double c = STORED ? ch[j] : unit_coef(P, sc, r, b + k, L);
                             U += c * vh[j];
                         } else {
                             D += nuc[b + k] * vh[j];

@@ -5,8 +5,10 @@ All arithmetic runs in libhq.so (batched solves, feature extraction, the
 network's forward/backward/Adam kernels); this module only orchestrates.
 
 * ``training_set``: solve a seeded pool of deployments (N ~ U{16..20},
-  J = 500, load ~ U[0.5, 0.9)) with one batched launch per chunk and return
-  the per-unit features with the solved busy probabilities as targets.
+  load ~ U[0.5, 0.9); uniform demand with J = 500, plus a share with four
+  Gaussian demand clusters, J = 1000 and mu ~ U[0.5, 1.5]) with one batched
+  launch per chunk and return the per-unit features with the solved busy
+  probabilities as targets.
 * ``train``: fit a fresh network on that set (Adam, minibatches, on the GPU).
 * ``heuristic_rho``: the baseline product-form seed, each unit as an M/M/1/1
   queue fed by the demand that ranks it first: a / (1 + a), a = load / nu.
@@ -37,13 +39,35 @@ def load_network(path: str = WEIGHTS, device: int = -1):
     return m
 
 
-def training_set(count: int, *, first_index: int = 1000, tol: float = 1e-7, chunk: int = 512,
-                 verbose: bool = False):
-    """Features X [rows, HQ_MLP_IN] and targets t [rows] (busy probabilities)."""
+CLUSTERED = dict(clusters=4, sigma=0.1, J=1000, nu_range=(0.5, 1.5))
+
+
+def pool_instance(i: int, count: int, clustered: float):
+    """Deployment i of a training pool of ``count``: the last
+    round(count * clustered) have clustered demand."""
+    n_uniform = count - int(round(count * clustered))
+    if i < n_uniform:
+        return config_instance(5, 1000 + i)
+    return config_instance(5, 200000 + i, **CLUSTERED)
+
+
+def training_set(count: int, *, clustered: float = 0.0, tol: float = 1e-7, chunk: int = 512,
+                 verbose: bool = False, targets: Optional[np.ndarray] = None):
+    """Features X [rows, HQ_MLP_IN] and targets t [rows] (busy probabilities).
+    With ``targets`` (the t of an earlier call on the same pool) nothing is
+    solved again: the features are rebuilt from the seeded deployments."""
     X: List[np.ndarray] = []
     t: List[np.ndarray] = []
+    if targets is not None:
+        for i in range(count):
+            inst = pool_instance(i, count, clustered)
+            X.append(hq.hq_mlp_features(inst.N, inst.J, inst.lam, inst.nu, inst.pref))
+        X = np.concatenate(X)
+        if X.shape[0] != targets.shape[0]:
+            raise ValueError("targets do not match this pool")
+        return X, np.asarray(targets, dtype=np.float32)
     for c0 in range(0, count, chunk):
-        insts = [config_instance(5, first_index + i) for i in range(c0, min(count, c0 + chunk))]
+        insts = [pool_instance(i, count, clustered) for i in range(c0, min(count, c0 + chunk))]
         ctxs = [hq.create_from_instance(i, inner=hq.HQ_INNER_ONE) for i in insts]
         t0 = time.perf_counter()
         hq.hq_solve_batch(ctxs, tol)
@@ -121,25 +145,34 @@ def summarize(res: Dict[str, list]) -> dict:
 def main(argv=None):
     """Train the shipped network on method-generated solves and evaluate it.
 
-    python -m paper_2603_03019_amd.warmstart --train 4096 --eval 100
+    python -m paper_2603_03019_amd.warmstart --train 20000 --clustered 0.2 --eval 100
     """
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=4096, help="training deployments to solve")
+    ap.add_argument("--train", type=int, default=20000, help="training deployments to solve")
+    ap.add_argument("--clustered", type=float, default=0.2, help="share of clustered-demand deployments")
     ap.add_argument("--eval", type=int, default=100, help="unseen N=24 deployments to evaluate")
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--summary", default="")
+    ap.add_argument("--targets", default="", help="solved targets of the pool: reused if the file exists, "
+                                                  "else written after solving")
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=1024)
     a = ap.parse_args(argv)
     t = time.perf_counter()
-    X, y = training_set(a.train, verbose=True)
+    cached = np.load(a.targets, allow_pickle=False) if a.targets and os.path.exists(a.targets) else None
+    X, y = training_set(a.train, clustered=a.clustered, verbose=True, targets=cached)
+    if a.targets and cached is None:
+        np.save(a.targets, y, allow_pickle=False)
     print(f"warmstart: {X.shape[0]} rows from {a.train} solves in {time.perf_counter() - t:.1f}s", flush=True)
     t = time.perf_counter()
-    net, losses = train(X, y, epochs=a.epochs)
+    net, losses = train(X, y, epochs=a.epochs, batch=a.batch, lr=a.lr)
     print(f"warmstart: trained in {time.perf_counter() - t:.1f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}",
           flush=True)
     os.makedirs(os.path.dirname(a.out), exist_ok=True)
     np.save(a.out, hq.hq_mlp_get_params(net).astype(np.float32), allow_pickle=False)
-    s = {"train_solves": a.train, "train_rows": int(X.shape[0]), "epochs": a.epochs,
+    s = {"train_solves": a.train, "train_clustered": a.clustered, "train_rows": int(X.shape[0]), "epochs": a.epochs,
+         "batch": a.batch, "lr": a.lr,
          "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
     if a.eval:
         s.update(summarize(evaluate(net, range(50000, 50000 + a.eval), verbose=True)))
