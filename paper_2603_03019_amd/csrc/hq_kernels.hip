@@ -250,7 +250,7 @@ struct SegScal {
 // the previous segment's work.
 struct SegVec {
     uint32_t seg;  // lane k < H: start of segment (T xor e_k, q); lanes H, H+1, H+2: (T, q-1), (T, q+1), (T, q)
-    uint32_t po;   // lane u <= N: prog_off[T][u]
+    uint32_t po;   // lane u <= N: prog_off[T][u] relative to the tile's first term
     double tc;     // lane u < N: tcoef[T][u]
     uint32_t pm;   // lane i: mask of program term i
     double pr;     //         and its rate
@@ -286,7 +286,7 @@ __device__ __forceinline__ SegVec fetch_vec(const SweepParams& P, int b, int H, 
     r.pm = 0u;
     r.pr = 0.0;
     if (stored) return r;
-    if (lane <= N) r.po = P.prog_off[(size_t)Tb * (N + 1) + lane];
+    if (lane <= N) r.po = P.prog_off[(size_t)Tb * (N + 1) + lane] - sc.pstart;
     if (lane < N) r.tc = P.tcoef[(size_t)Tb * N + lane];
     if ((uint32_t)lane < sc.pcount) {
         const ProgTerm t = P.prog[sc.pstart + lane];
@@ -303,7 +303,7 @@ __device__ __forceinline__ SegVec fetch_vec(const SweepParams& P, int b, int H, 
 __device__ __forceinline__ double unit_coef(const SweepParams& P, const SegScal& sc, const SegVec& r, int u,
                                             uint32_t L) {
     double c = bcast(r.tc, (uint32_t)u);
-    const uint32_t i0 = bcast(r.po, (uint32_t)u) - sc.pstart, i1 = bcast(r.po, (uint32_t)u + 1u) - sc.pstart;
+    const uint32_t i0 = bcast(r.po, (uint32_t)u), i1 = bcast(r.po, (uint32_t)u + 1u);
     const uint32_t nL = ~L;
     const uint32_t ireg = i1 < HQ_PROG_REG ? i1 : HQ_PROG_REG;
     for (uint32_t i = i0; i < ireg; ++i) {
