@@ -91,6 +91,63 @@ def _layer_update_parity(inst, pop, mu_m):
         assert rel.max() <= 1e-11, (n, rel.max())
 
 
+def test_maximum_size_layer_update():
+    # N = 30 (HQ_MAX_N, 2^30 states, b = 12, H = 18): the same check, with
+    # the layer sums of the exported snapshots taken by plain torch
+    # reductions on the device (2^30-entry host passes would take minutes)
+    import time
+
+    import torch
+
+    inst = config_instance(3, 0, N=30)
+    N, Lam = inst.N, inst.Lambda
+    t0 = time.perf_counter()
+    say("case N=30 layer update: create")
+    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE)
+    say(f"  created in {time.perf_counter() - t0:.1f}s; iterate")
+    hq.hq_iterate(ctx, 2)
+    S1 = hq.hq_conditional(ctx)
+    t1 = time.perf_counter()
+    hq.hq_iterate(ctx, 1)
+    say(f"  one outer iteration {time.perf_counter() - t1:.3f}s; export")
+    S2 = hq.hq_conditional(ctx)
+    hq.hq_destroy(ctx)
+    say("  layer sums on the device")
+    m = torch.arange(1 << N, device="cuda", dtype=torch.int64)
+    pop = torch.zeros_like(m)
+    mu_m = torch.zeros(1 << N, device="cuda", dtype=torch.float64)
+    for u in range(N):
+        bit = (m >> u) & 1
+        pop += bit
+        mu_m += float(inst.nu[u]) * bit.to(torch.float64)
+    del m, bit
+    sums = {}
+    for name, S in (("S1", S1), ("S2", S2)):
+        t = torch.from_numpy(S).to("cuda")
+        lam_sum = torch.bincount(pop, weights=t, minlength=N + 1).cpu().numpy()
+        mu_sum = torch.bincount(pop, weights=t * mu_m, minlength=N + 1).cpu().numpy()
+        sums[name] = (lam_sum, mu_sum)
+        del t
+    del pop, mu_m
+    torch.cuda.synchronize()
+
+    def lam_of(name, n):
+        return 0.0 if n == N else Lam * sums[name][0][n]
+
+    def mu_of(name, n):
+        return float(sums[name][1][n])
+
+    rng = np.random.default_rng(0)
+    for n in (1, 3, 9, N // 2, N - 9, N - 6, N - 2, N - 1):
+        say(f"case N={N} layer {n}")
+        alpha = mu_of("S1", n) / lam_of("S2", n - 1)
+        beta = lam_of("S1", n) / mu_of("S1", n + 1)
+        states = _sample_layer(rng, N, n, 1500)
+        want, _, _ = cpu.update_states(inst, states, S2, S1, alpha, beta)
+        rel = np.abs(S2[states] - want) / np.abs(want)
+        assert rel.max() <= 1e-11, (n, rel.max())
+
+
 def test_full_size_converged_balance_and_marginals(big):
     inst, pop, mu_m = big
     say("case N=26 solve to 1e-8")
