@@ -277,8 +277,8 @@ def main():
                     help="only run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not "
-              "part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver runs each "
+              "instance on one device and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
