@@ -37,8 +37,9 @@ hipError_t launch_dispatch(double* G, int N, int J, const int32_t* pref, double*
 hipError_t launch_widen(const float* src, double* dst, uint32_t begin, uint32_t count, double factor,
                         hipStream_t s);
 hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, uint32_t nnodes, hipStream_t s);
-hipError_t launch_batch(bool fp32, int block, const BatchItem* items, BatchOut* outs, int count,
-                        unsigned int* next, int grid, hipStream_t s);
+hipError_t launch_batch(bool fp32, int block, const BatchItem* items, const BatchEntry* entries, BatchOut* outs,
+                        int count, unsigned int* next, unsigned int* group_counts, int n_items, int grid,
+                        hipStream_t s);
 }  // namespace hqk
 
 // automatic choice of stored-coefficient layers (see hq_create)
@@ -762,11 +763,14 @@ struct BatchRes {
     BatchItem* items = nullptr;
     BatchOut* outs = nullptr;
     unsigned int* next = nullptr;
+    BatchEntry* entries = nullptr;      // work queue, up to HQ_GROUP_MAX entries per instance
+    unsigned int* group_counts = nullptr;  // one barrier counter per instance
+    double* group_parts = nullptr;      // [cap][2][HQ_GROUP_MAX][3]
     int cap = 0;
     hipStream_t stream = nullptr;
     struct Graph {
         bool fp32;
-        int block, count, grid;
+        int block, count, items, grid;
         hipGraphExec_t exec;
     };
     std::vector<Graph> graphs;
@@ -783,42 +787,50 @@ BatchRes& batch_res(int device, int count) {
         r.graphs.clear();
         if (r.items) (void)hipFree(r.items);
         if (r.outs) (void)hipFree(r.outs);
+        if (r.entries) (void)hipFree(r.entries);
+        if (r.group_counts) (void)hipFree(r.group_counts);
+        if (r.group_parts) (void)hipFree(r.group_parts);
         if (!r.next) r.next = dalloc<unsigned int>(1);
         r.cap = std::max(count, 64);
         r.items = dalloc<BatchItem>(r.cap);
         r.outs = dalloc<BatchOut>(r.cap);
+        r.entries = dalloc<BatchEntry>((size_t)r.cap * HQ_GROUP_MAX);
+        r.group_counts = dalloc<unsigned int>(r.cap);
+        r.group_parts = dalloc<double>((size_t)r.cap * 2 * HQ_GROUP_MAX * 3);
     }
     return r;
 }
 
-// One launch of the batch kernel (reset of the work counter + the
-// persistent kernel) as a captured hipGraph, reused for equal shapes.
-void batch_launch(BatchRes& r, bool fp32, int block, int count, int grid) {
+// One launch of the batch kernel (reset of the work counter and of the
+// group barrier counters, then the persistent kernel) as a captured
+// hipGraph, reused for equal shapes.  `count` is the number of queue entries.
+void batch_launch(BatchRes& r, bool fp32, int block, int count, int n_items, int grid) {
     for (auto& g : r.graphs)
-        if (g.fp32 == fp32 && g.block == block && g.count == count && g.grid == grid) {
+        if (g.fp32 == fp32 && g.block == block && g.count == count && g.items == n_items && g.grid == grid) {
             HQ_HIP(hipGraphLaunch(g.exec, r.stream));
             return;
         }
     hipGraph_t graph = nullptr;
     HQ_HIP(hipStreamBeginCapture(r.stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = hqk::launch_batch(fp32, block, r.items, r.outs, count, r.next, grid, r.stream);
+    hipError_t le = hqk::launch_batch(fp32, block, r.items, r.entries, r.outs, count, r.next, r.group_counts,
+                                      n_items, grid, r.stream);
     hipError_t ce = hipStreamEndCapture(r.stream, &graph);
     HQ_HIP(le);
     HQ_HIP(ce);
     hipGraphExec_t exec = nullptr;
     HQ_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     (void)hipGraphDestroy(graph);
-    r.graphs.push_back({fp32, block, count, grid, exec});
+    r.graphs.push_back({fp32, block, count, n_items, grid, exec});
     HQ_HIP(hipGraphLaunch(exec, r.stream));
 }
 
-int batch_grid(int count) {
+int device_cus() {
     int cus = 256;
     hipDeviceProp_t prop;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         cus = prop.multiProcessorCount;
-    return std::max(1, std::min(count, cus * 2));
+    return std::max(1, cus);
 }
 
 hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& pos, bool fp32, double tol,
@@ -853,7 +865,31 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
     }
     std::lock_guard<std::mutex> lock(g_batch_mu);
     BatchRes& r = batch_res(device, count);
-    const int grid = batch_grid(count);
+    const int cus = device_cus();
+    // Work sharing: an instance gets k work-groups, about its share of all
+    // states times the compute units (at most HQ_GROUP_MAX), so that the largest
+    // instances do not leave the rest of the device idle.  Its k ranks are
+    // consecutive queue entries (largest instances first), which keeps the
+    // queue free of deadlock: a rank is only ever taken by a running
+    // work-group, and only the group at the head of the queue can be
+    // partly taken.
+    std::vector<BatchEntry> entries;
+    {
+        double total = 0.0;
+        for (int j = 0; j < count; ++j) total += std::ldexp(1.0, cs[order[j]]->N);
+        const double share = total / cus;
+        for (int j = 0; j < count; ++j) {
+            const double w = std::ldexp(1.0, cs[order[j]]->N);
+            const int k = (int)std::min<double>(HQ_GROUP_MAX, std::max(1.0, std::round(w / share)));
+            items[j].group_count = r.group_counts + j;
+            items[j].group_part = r.group_parts + (size_t)j * 2 * HQ_GROUP_MAX * 3;
+            for (int rk = 0; rk < k; ++rk) entries.push_back(BatchEntry{j, rk, k, 0});
+        }
+    }
+    const int n_entries = (int)entries.size();
+    const int grid = std::max(1, std::min(n_entries, 2 * cus));
+    HQ_HIP(hipMemcpyAsync(r.entries, entries.data(), sizeof(BatchEntry) * n_entries, hipMemcpyHostToDevice,
+                          r.stream));
     // autotuner: time each work-group size on this batch (a few iterations)
     std::string sig = std::string(fp32 ? "f32" : "f64") + ":" + std::to_string(count);
     {
@@ -878,9 +914,9 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
         HQ_HIP(hipEventCreate(&e1));
         float best = 1e30f;
         for (int bs : {256, 512, 1024}) {
-            batch_launch(r, fp32, bs, count, grid);  // warm-up (graph build)
+            batch_launch(r, fp32, bs, n_entries, count, grid);  // warm-up (graph build)
             HQ_HIP(hipEventRecord(e0, r.stream));
-            batch_launch(r, fp32, bs, count, grid);
+            batch_launch(r, fp32, bs, n_entries, count, grid);
             HQ_HIP(hipEventRecord(e1, r.stream));
             HQ_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -900,7 +936,7 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
     HQ_HIP(hipEventCreate(&k0));
     HQ_HIP(hipEventCreate(&k1));
     HQ_HIP(hipEventRecord(k0, r.stream));
-    batch_launch(r, fp32, block, count, grid);
+    batch_launch(r, fp32, block, n_entries, count, grid);
     HQ_HIP(hipEventRecord(k1, r.stream));
     std::vector<BatchOut> outs(count);
     HQ_HIP(hipMemcpyAsync(outs.data(), r.outs, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, r.stream));

@@ -86,8 +86,11 @@ struct LayerArgs {
     int init_mode;
 };
 
+// Largest number of work-groups that share one instance of a batch.
+#define HQ_GROUP_MAX 16
+
 // One instance of a batched solve: everything the persistent batch kernel
-// needs to run Algorithm 1 on it inside one work-group.
+// needs to run Algorithm 1 on it, in one work-group or in a group of them.
 struct BatchItem {
     SweepParams P;
     LayerArgs layers[31];     // n = 0..N
@@ -100,6 +103,15 @@ struct BatchItem {
     const double* xu;         // product-form x_u (relabelled)
     const double* given;      // given state (original bitmask order)
     const uint32_t* orig_bit; // relabelled unit -> original bit
+    unsigned int* group_count; // arrivals at the group's barriers (zeroed per launch)
+    double* group_part;        // [2][HQ_GROUP_MAX][3] per-work-group partial sums, double-buffered
+};
+
+// One entry of the batch work queue: rank `rank` of the `k` work-groups
+// that share instance `item` (k = 1: the instance runs in one work-group).
+// The ranks of an instance are consecutive entries.
+struct BatchEntry {
+    int item, rank, k, pad;
 };
 
 // Per-instance results of a batched solve.

@@ -32,6 +32,7 @@
 
 namespace hq {
 
+#define HQ_ERR_DEVICE_CODE 3
 #define HQ_ERR_NOT_CONVERGED_CODE 4
 #define HQ_ERR_NUMERIC_CODE 5
 
@@ -896,37 +897,110 @@ __device__ __forceinline__ void block_sum3(double& a0, double& a1, double& a2, d
     a2 = b2;
 }
 
+// One layer of one instance inside the batch kernel: the waves of the
+// work-groups sharing the instance take its segments round-robin, wave w of
+// rank r starting at segment r * waves + w.
 template <typename T, int MODE>
 __device__ __forceinline__ void batch_layer(const SweepParams& P, const LayerArgs& A, T* x, const uint16_t* s_rank,
                                             const uint16_t* s_unrank, const uint32_t* s_qstart,
-                                            const ModeScalars& ms, double& a0, double& a1, double& a2) {
-    const uint32_t NW = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+                                            const ModeScalars& ms, uint32_t first, uint32_t stride, double& a0,
+                                            double& a1, double& a2) {
     if (A.stored) {
-        for (uint32_t si = wv; si < A.groups; si += NW)
+        for (uint32_t si = first; si < A.groups; si += stride)
             segment_update<T, MODE, false, true>(P, A, x, si, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
     } else {
-        for (uint32_t si = wv; si < A.groups; si += NW)
+        for (uint32_t si = first; si < A.groups; si += stride)
             segment_update<T, MODE, false, false>(P, A, x, si, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
     }
 }
 
+// The k work-groups that share one batch instance.  `epoch` counts the
+// barriers this work-group has passed; the group's counter only grows, so
+// barrier e is passed once it reaches e * k.
+struct GroupCtx {
+    unsigned int* count;
+    double* part;
+    int k, rank;
+    unsigned int epoch;
+    int ok;  // 0 once a barrier wait ran out (the instance then stops)
+};
+
+// Barrier of the work-groups of one instance: the usual device-wide
+// pattern (work-group barrier, agent-scope release, arrival, bounded wait,
+// agent-scope acquire, work-group barrier), so the state-vector writes and
+// partials of every member are visible to all of them afterwards.  A wait
+// that runs out of spins marks the group failed instead of hanging.
+#define HQ_GROUP_SPINS (1u << 22)
+__device__ __forceinline__ void group_barrier(GroupCtx& g, int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int target = (g.epoch + 1u) * (unsigned int)g.k;
+        int ok = g.ok;
+        __threadfence();
+        __hip_atomic_fetch_add(g.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned int spins = 0;
+        while (ok && __hip_atomic_load(g.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > HQ_GROUP_SPINS) ok = 0;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        *s_flag = ok;
+    }
+    __syncthreads();
+    g.ok = *s_flag;
+    g.epoch += 1u;
+}
+
+// Block totals of (sum, sum, max), then, for a group, the totals over its
+// work-groups: each writes its totals to its slot of the current buffer,
+// and after the barrier every member adds the k slots in rank order, so all
+// members hold bitwise the same totals.
+template <int BS>
+__device__ __forceinline__ void group_sum3(double& a0, double& a1, double& a2, double (*s_red)[BS / 64],
+                                          GroupCtx& g, int* s_flag) {
+    block_sum3<BS>(a0, a1, a2, s_red);
+    if (g.k == 1) return;
+    double* buf = g.part + (size_t)(g.epoch & 1u) * (HQ_GROUP_MAX * 3);
+    if (threadIdx.x == 0) {
+        buf[g.rank * 3 + 0] = a0;
+        buf[g.rank * 3 + 1] = a1;
+        buf[g.rank * 3 + 2] = a2;
+    }
+    group_barrier(g, s_flag);
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    for (int r = 0; r < g.k; ++r) {
+        b0 += __hip_atomic_load(buf + r * 3 + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b1 += __hip_atomic_load(buf + r * 3 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b2 = fmax(b2, __hip_atomic_load(buf + r * 3 + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    a0 = b0;
+    a1 = b1;
+    a2 = b2;
+}
+
 template <typename T, int BS>
-__global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__ items, BatchOut* __restrict__ outs,
+__global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__ items,
+                                                   const BatchEntry* __restrict__ entries, BatchOut* __restrict__ outs,
                                                    int count, unsigned int* __restrict__ next) {
     __shared__ uint16_t s_rank[1 << HQ_MAXB];
     __shared__ uint16_t s_unrank[1 << HQ_MAXB];
     __shared__ uint32_t s_qstart[HQ_MAXB + 2];
     __shared__ double s_lam[32], s_mu[32], s_alpha[32], s_pn[32];
     __shared__ double s_red[3][BS / 64];
-    __shared__ int s_item, s_go, s_next;
+    __shared__ int s_item, s_go, s_next, s_flag;
     const int tid = threadIdx.x;
+    const uint32_t NW = BS / 64, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (;;) {
         __syncthreads();
         if (tid == 0) s_item = (int)__hip_atomic_fetch_add(next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int ii = __builtin_amdgcn_readfirstlane(s_item);
-        if (ii >= count) break;
+        const int ei = __builtin_amdgcn_readfirstlane(s_item);
+        if (ei >= count) break;
+        const BatchEntry E = entries[ei];
+        const int ii = E.item;
         const BatchItem& B = items[ii];
+        GroupCtx g{B.group_count, B.group_part, E.k, E.rank, 0u, 1};
+        const uint32_t first = (uint32_t)E.rank * NW + wv, stride = (uint32_t)E.k * NW;
         const SweepParams& P = B.P;
         T* x = (T*)B.x;
         const int N = P.N, b = P.b;
@@ -939,10 +1013,9 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
         // initial iterate and its layer scalars (13)-(14)
         for (int n = 0; n <= N; ++n) {
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            const uint32_t NW = BS / 64, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-            for (uint32_t si = wv; si < B.layers[n].groups; si += NW)
+            for (uint32_t si = first; si < B.layers[n].groups; si += stride)
                 init_segment<T>(P, B.layers[n], x, si, B.init_mode, B.xu, B.given, B.orig_bit, a0, a1);
-            block_sum3<BS>(a0, a1, a2, s_red);
+            group_sum3<BS>(a0, a1, a2, s_red, g, &s_flag);
             if (tid == 0) {
                 s_lam[n] = (n == N) ? 0.0 : P.Lam * a0;
                 s_mu[n] = a1;
@@ -960,15 +1033,15 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
                 if (!B.inner_one) {
                     const ModeScalars ms = mode_scalars<M_PASS1>(P, n, 0, s_lam, s_mu, s_alpha, s_pn);
                     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-                    batch_layer<T, M_PASS1>(P, A, x, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
-                    block_sum3<BS>(a0, a1, a2, s_red);
+                    batch_layer<T, M_PASS1>(P, A, x, s_rank, s_unrank, s_qstart, ms, first, stride, a0, a1, a2);
+                    group_sum3<BS>(a0, a1, a2, s_red, g, &s_flag);
                     if (tid == 0) s_alpha[n] = ms.beta * a1 / (P.Lam * a0);
                     __syncthreads();
                 }
                 const ModeScalars ms = mode_scalars<M_WRITE>(P, n, B.inner_one, s_lam, s_mu, s_alpha, s_pn);
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-                batch_layer<T, M_WRITE>(P, A, x, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
-                block_sum3<BS>(a0, a1, a2, s_red);
+                batch_layer<T, M_WRITE>(P, A, x, s_rank, s_unrank, s_qstart, ms, first, stride, a0, a1, a2);
+                group_sum3<BS>(a0, a1, a2, s_red, g, &s_flag);
                 if (tid == 0) {
                     s_alpha[n] = ms.alpha;
                     s_lam[n] = P.Lam * a0;
@@ -987,14 +1060,18 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
             for (int n = 0; n <= N; ++n) {
                 const ModeScalars ms = mode_scalars<M_RESID>(P, n, 0, s_lam, s_mu, s_alpha, s_pn);
-                batch_layer<T, M_RESID>(P, B.layers[n], x, s_rank, s_unrank, s_qstart, ms, a0, a1, a2);
+                batch_layer<T, M_RESID>(P, B.layers[n], x, s_rank, s_unrank, s_qstart, ms, first, stride, a0, a1,
+                                        a2);
             }
-            block_sum3<BS>(a0, a1, a2, s_red);
+            group_sum3<BS>(a0, a1, a2, s_red, g, &s_flag);
             ++checks;
             if (tid == 0) {
                 res = a1 > 0.0 ? a0 / a1 : 0.0;
                 int go = 1;
-                if (!isfinite(res)) {
+                if (!g.ok) {
+                    status = HQ_ERR_DEVICE_CODE;
+                    go = 0;
+                } else if (!isfinite(res)) {
                     status = HQ_ERR_NUMERIC_CODE;
                     go = 0;
                 } else if (res <= B.tol) {
@@ -1023,7 +1100,7 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
             if (!s_go) break;
         }
         // publish the instance's scalars where the single-instance entry points read them
-        if (tid == 0) {
+        if (tid == 0 && E.rank == 0) {
             double wmean = 0.0;
             const double wmass = birth_death(P, s_lam, s_mu, s_pn, &wmean);
             double mass = wmass;
@@ -1134,6 +1211,10 @@ __global__ __launch_bounds__(256) void travel_kernel(const double* __restrict__ 
 
 __global__ void reset_counter_kernel(unsigned int* c) {
     if (threadIdx.x == 0) *c = 0u;
+}
+
+__global__ void zero_counters_kernel(unsigned int* c, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
 }
 
 }  // namespace hq
@@ -1271,15 +1352,18 @@ hipError_t launch_marginal(bool fp32, const SweepParams& P, const LayerArgs& A, 
     return hipGetLastError();
 }
 
-hipError_t launch_batch(bool fp32, int block, const BatchItem* items, BatchOut* outs, int count,
-                        unsigned int* next, int grid, hipStream_t s) {
+hipError_t launch_batch(bool fp32, int block, const BatchItem* items, const BatchEntry* entries, BatchOut* outs,
+                        int count, unsigned int* next, unsigned int* group_counts, int n_items, int grid,
+                        hipStream_t s) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, next);
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(n_items > 0 ? (n_items + 255) / 256 : 1), dim3(256), 0, s,
+                       group_counts, n_items);
 #define HQ_BATCH_CASE(BSZ)                                                                                    \
     case BSZ:                                                                                               \
         if (fp32)                                                                                           \
-            hipLaunchKernelGGL((batch_kernel<float, BSZ>), dim3(grid), dim3(BSZ), 0, s, items, outs, count, next); \
+            hipLaunchKernelGGL((batch_kernel<float, BSZ>), dim3(grid), dim3(BSZ), 0, s, items, entries, outs, count, next); \
         else                                                                                                \
-            hipLaunchKernelGGL((batch_kernel<double, BSZ>), dim3(grid), dim3(BSZ), 0, s, items, outs, count, next); \
+            hipLaunchKernelGGL((batch_kernel<double, BSZ>), dim3(grid), dim3(BSZ), 0, s, items, entries, outs, count, next); \
         break;
     switch (block) {
         HQ_BATCH_CASE(256)
