@@ -19,6 +19,7 @@
 
 #include "hq.h"
 #include "hq_internal.h"
+#include "hq_batchplan.h"
 #include "hq_init.h"
 #include "hq_layout.h"
 
@@ -866,25 +867,18 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
     std::lock_guard<std::mutex> lock(g_batch_mu);
     BatchRes& r = batch_res(device, count);
     const int cus = device_cus();
-    // Work sharing: an instance gets k work-groups, about its share of all
-    // states times the compute units (at most HQ_GROUP_MAX), so that the largest
-    // instances do not leave the rest of the device idle.  Its k ranks are
-    // consecutive queue entries (largest instances first), which keeps the
-    // queue free of deadlock: a rank is only ever taken by a running
-    // work-group, and only the group at the head of the queue can be
-    // partly taken.
+    // Work sharing (hq_batchplan.h): an instance gets k work-groups, so that
+    // the largest instances do not leave the rest of the device idle.
     std::vector<BatchEntry> entries;
     {
-        double total = 0.0;
-        for (int j = 0; j < count; ++j) total += std::ldexp(1.0, cs[order[j]]->N);
-        const double share = total / cus;
+        std::vector<double> sizes(count);
         for (int j = 0; j < count; ++j) {
-            const double w = std::ldexp(1.0, cs[order[j]]->N);
-            const int k = (int)std::min<double>(HQ_GROUP_MAX, std::max(1.0, std::round(w / share)));
+            sizes[j] = std::ldexp(1.0, cs[order[j]]->N);
             items[j].group_count = r.group_counts + j;
             items[j].group_part = r.group_parts + (size_t)j * 2 * HQ_GROUP_MAX * 3;
-            for (int rk = 0; rk < k; ++rk) entries.push_back(BatchEntry{j, rk, k, 0});
         }
+        for (const hqplan::Entry& e : hqplan::plan(sizes, cus, HQ_GROUP_MAX))
+            entries.push_back(BatchEntry{e.item, e.rank, e.k, 0});
     }
     const int n_entries = (int)entries.size();
     const int grid = std::max(1, std::min(n_entries, 2 * cus));
