@@ -217,6 +217,10 @@ hq_status hq_state(const hq_ctx* ctx, double* P);
  * created with HQ_FP64 or HQ_FP32 storage, the residual stopping rule and the
  * closed or one-update inner form (HQ_ERR_INVALID_ARG otherwise).  infos
  * (nullable) [count].
+ * A large instance is shared by up to 16 work-groups that meet at a barrier
+ * after every layer; the results agree with hq_solve to rounding, and a
+ * repeated batch gives bitwise the same results.  A barrier wait that runs
+ * out (a device fault) ends that instance with HQ_ERR_DEVICE.
  * Returns HQ_OK only if every instance converged; per-instance statuses are
  * in infos.
  */
