@@ -83,3 +83,20 @@ def test_batch_rejects_polish_contexts():
     with pytest.raises(hq.HQError) as e:
         hq.hq_solve_batch([c], 1e-8)
     assert e.value.status == hq.HQ_ERR_INVALID_ARG
+
+
+def test_batch_product_start_matches_oracle():
+    # product-form starts fitted to the exact utilisations, in a batch whose
+    # largest instance is shared by several work-groups
+    insts = [config_instance(4, 70 + i, N=n) for i, n in enumerate([16, 12, 13, 11])]
+    say(f"case batch product start sizes={[i.N for i in insts]}")
+    refs = [cpu.solve(inst, tol=1e-12) for inst in insts]
+    ctxs = [hq.create_from_instance(inst, init_rho=cpu.marginals(inst.N, ref.P)[0])
+            for inst, ref in zip(insts, refs)]
+    cold = [hq.create_from_instance(inst) for inst in insts]
+    st, infos = hq.hq_solve_batch(ctxs, 1e-11)
+    assert st == hq.HQ_OK
+    _, cold_infos = hq.hq_solve_batch(cold, 1e-11)
+    for inst, ref, ctx, info, ci in zip(insts, refs, ctxs, infos, cold_infos):
+        assert np.abs(hq.hq_state(ctx) - ref.P).sum() <= 1e-9, inst.N
+        assert info["iterations"] <= ci["iterations"]
