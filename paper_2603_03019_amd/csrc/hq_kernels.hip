@@ -1234,8 +1234,8 @@ static uint32_t grid_for(uint32_t groups) {
 }
 
 // Fixed-shape kernels for the default tiles of the larger instances (b = 10
-// for N = 16..27, b = 12 for N = 28..30): the sweep (with computed or
-// stored coefficients) and the residual.  Other shapes and modes use the
+// for N = 16..30) and for b = 12 at N = 28..30: the sweep (with computed
+// or stored coefficients) and the residual.  Other shapes and modes use the
 // run-time-shaped kernels.
 template <typename T, int BF, int HF>
 static void launch_fixed(int mode, bool stored, bool track, const SweepParams& P, const LayerArgs& A, T* x,
@@ -1268,7 +1268,7 @@ static bool launch_layer_fixed(int mode, bool stored, bool track, const SweepPar
     }
     HQ_FIXED(10, 6) HQ_FIXED(10, 7) HQ_FIXED(10, 8) HQ_FIXED(10, 9) HQ_FIXED(10, 10) HQ_FIXED(10, 11)
     HQ_FIXED(10, 12) HQ_FIXED(10, 13) HQ_FIXED(10, 14) HQ_FIXED(10, 15) HQ_FIXED(10, 16) HQ_FIXED(10, 17)
-    HQ_FIXED(12, 16) HQ_FIXED(12, 17) HQ_FIXED(12, 18)
+    HQ_FIXED(10, 18) HQ_FIXED(10, 19) HQ_FIXED(10, 20) HQ_FIXED(12, 16) HQ_FIXED(12, 17) HQ_FIXED(12, 18)
 #undef HQ_FIXED
     return false;
 }

@@ -55,19 +55,19 @@ def test_full_size_layer_update(big):
     _layer_update_parity(*big)
 
 
-@pytest.mark.parametrize("N", [27, 28])
-def test_larger_tile_shapes_layer_update(N):
-    # N = 27 runs the b = 10, H = 17 kernels and N = 28 the b = 12, H = 16
-    # ones (the tile width grows to 12 bits from N = 28)
+@pytest.mark.parametrize("N,tile_bits", [(27, 0), (28, 0), (28, 12)])
+def test_larger_tile_shapes_layer_update(N, tile_bits):
+    # default 10-bit tiles: the b = 10, H = 17 and H = 18 kernels; and the
+    # 12-bit tiles a caller can choose (b = 12, H = 16)
     inst = config_instance(3, 0, N=N)
-    say(f"case N={N} tables")
-    _layer_update_parity(inst, *_tables(inst))
+    say(f"case N={N} tile_bits={tile_bits} tables")
+    _layer_update_parity(inst, *_tables(inst), tile_bits=tile_bits)
 
 
-def _layer_update_parity(inst, pop, mu_m):
+def _layer_update_parity(inst, pop, mu_m, tile_bits=0):
     N, Lam = inst.N, inst.Lambda
     say(f"case N={N} layer update: iterate")
-    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE)
+    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE, tile_bits=tile_bits)
     hq.hq_iterate(ctx, 2)
     S1 = hq.hq_conditional(ctx)
     hq.hq_iterate(ctx, 1)
@@ -92,7 +92,7 @@ def _layer_update_parity(inst, pop, mu_m):
 
 
 def test_maximum_size_layer_update():
-    # N = 30 (HQ_MAX_N, 2^30 states, b = 12, H = 18): the same check, with
+    # N = 30 (HQ_MAX_N, 2^30 states, b = 10, H = 20): the same check, with
     # the layer sums of the exported snapshots taken by plain torch
     # reductions on the device (2^30-entry host passes would take minutes)
     import time
