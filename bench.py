@@ -11,9 +11,10 @@ Prints one JSON line (rank 0).  Besides value / ms_per_step it carries:
   roofline      the layer-sweep kernels' algorithmic HBM bytes per outer
                 iteration over their device time per iteration (HIP events
                 on the library's stream around the sweeps);
-  cpu_baseline  the CPU FP64 oracle on a bounded sample of the same
-                workload: one layer update (12) of a sample of middle-layer
-                states with Algorithm-3 coefficients generated per state.
+  cpu_baseline  the CPU FP64 oracle's Algorithm 1 on the same deployment,
+                timed on a block of middle-layer states (coefficient step
+                and outer-iteration updates) at one thread and at every
+                host thread, scaled to the full state space.
 """
 import argparse
 import json
@@ -77,41 +78,78 @@ def _sample_layer_states(rng, N: int, n: int, k: int):
     return np.bitwise_or.reduce(np.left_shift(np.uint32(1), bits), axis=1).astype(np.uint32)
 
 
-def cpu_baseline(inst, seconds_target: float = 15.0):
-    import numpy as np
+def _oracle_rates(cpu, inst, n: int, threads: int, coef_target_s: float, update_target_s: float):
+    """Per-state seconds of Algorithm 1's step 2 (coefficients by Algorithm
+    3) and of one outer-iteration update, timed by the oracle on a block of
+    consecutive layer-n states, the block sized to take about the target times."""
+    first = math.comb(inst.N, n) // 3
+    probe = cpu.time_sample(inst, n, first, 2000, 2, threads)
+    per_coef = max(probe["coef_s"] / 2000, 1e-9)
+    count = int(min(math.comb(inst.N, n) - first, max(2000, coef_target_s / per_coef)))
+    per_upd = max(probe["update_s"] / 2000, 1e-10)
+    reps = int(max(1, min(50, update_target_s / (per_upd * count))))
+    r = cpu.time_sample(inst, n, first, count, reps, threads)
+    return r["coef_s"] / count, r["update_s"] / count, r["threads"], count, reps
 
+
+def cpu_baseline(inst, iterations: int, checks: int):
+    """The CPU oracle's Algorithm 1 on the same deployment, at one thread and
+    at every host thread.  A full oracle solve at 2^26 states takes about an
+    hour, so the oracle times its own code on a block of middle-layer states
+    (step 2's coefficient generation, then outer-iteration updates: the
+    same functions its solve runs) and the figures are scaled to the whole
+    state space and to the iteration count the GPU solve needed."""
     from oracle import cpu
 
     cpu.build(force=False)
     N = inst.N
     n = N // 2
+    S = (1 << N) - 2
+    legs = {}
+    for threads in (1, cpu.threads()):
+        if threads in legs:
+            continue
+        per_coef, per_upd, used, count, reps = _oracle_rates(cpu, inst, n, threads, 4.0, 3.0)
+        coef_s = per_coef * (1 << N)
+        iter_s = per_upd * S
+        legs[used] = {
+            "value": 1.0 / per_upd,
+            "unit": "state-updates/s",
+            "cores": used,
+            "coef_s": coef_s,
+            "iter_s": iter_s,
+            "time_to_tol_s": coef_s + (iterations + checks) * iter_s,
+            "sample": f"{count} consecutive layer-{n} states, {reps} update reps",
+        }
+    top = legs[max(legs)]
+    one = legs[min(legs)]
+    # the old figure: one update (12) of sampled states with the coefficients
+    # generated per state (what a solve pays when it stores no coefficients)
+    import numpy as np
+
     rng = np.random.default_rng(0)
-    S = 1 << N
-    # neighbour layers: any positive values (the timing does not depend on them)
-    pl = rng.random(S)
-    pu = pl
-    probe = _sample_layer_states(rng, N, n, 20000)
+    states = _sample_layer_states(rng, N, n, 200000)
+    p = np.full(1 << N, 1.0 / math.comb(N, n))
     t = time.perf_counter()
-    cpu.update_states(inst, probe, pl, pu, 1.0, 1.0)
-    dt = max(time.perf_counter() - t, 1e-6)
-    chunk = int(min(4_000_000, max(20000, 20000 * 2.0 / dt)))  # about 2 s per call
-    states = _sample_layer_states(rng, N, n, chunk)
-    k = 0
-    t = time.perf_counter()
-    while True:
-        cpu.update_states(inst, states, pl, pu, 1.0, 1.0)
-        k += chunk
-        dt = time.perf_counter() - t
-        if dt >= seconds_target:
-            break
+    cpu.update_states(inst, states, p, p, 1.0, 1.0)
+    on_demand = len(states) / (time.perf_counter() - t)
+    del p
     return {
-        "value": k / dt,
+        "value": top["value"],
         "unit": "state-updates/s",
-        "cores": cpu.threads(),
+        "cores": top["cores"],
         "kind": "oracle",
-        "sample": f"one update (12) of {k} uniformly sampled layer-{n} states of the same N={N}, "
-                  f"J={inst.J} instance (Algorithm-3 coefficients generated per state), {dt:.1f} s "
-                  f"on {cpu.threads()} threads",
+        "sample": f"Algorithm 1 of the FP64 oracle on the same N={N}, J={inst.J} deployment, timed on "
+                  f"{top['sample']} (coefficient step and outer-iteration updates, the functions its "
+                  f"solve runs) and scaled to 2^{N} states; time_to_tol_s = coef_s + (iterations + "
+                  f"residual checks of the GPU solve = {iterations} + {checks}) x iter_s",
+        "time_to_tol_s": top["time_to_tol_s"],
+        "coef_s": top["coef_s"],
+        "iter_s": top["iter_s"],
+        "single_thread": one,
+        "on_demand_update": {"value": on_demand, "unit": "state-updates/s", "cores": cpu.threads(),
+                             "note": "one update (12) of 200000 sampled layer states with the "
+                                     "coefficients generated per state (no step 2)"},
     }
 
 
@@ -383,7 +421,8 @@ def main():
         out["batched"] = batched_leg(hq, config_instance, args.tol)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", flush=True)
-        out["cpu_baseline"] = cpu_baseline(inst)
+        out["cpu_baseline"] = cpu_baseline(inst, round(iters / args.steps),
+                                           round(sum(x["checks"] for x in infos) / args.steps))
     print(json.dumps(out), flush=True)
 
 

@@ -149,7 +149,10 @@ hq_status hq_create(int N, int J, const double* lambda_j, const double* mu_i,
 /*
  * Run Algorithm 1 from the configured initial iterate until the stopping
  * rule holds (tol > 0) or max_iters.  info (nullable) receives the
- * statistics.  Returns HQ_OK, HQ_ERR_NOT_CONVERGED (iterate still readable),
+ * statistics.  A solve whose residual has stopped falling (six checks in a
+ * row with less than a 0.01 % decrease per iteration: the rounding floor of
+ * FP64 above tol, or divergence) ends early with HQ_ERR_NOT_CONVERGED and
+ * the residual reached.  Returns HQ_OK, HQ_ERR_NOT_CONVERGED (iterate still readable),
  * HQ_ERR_NUMERIC, HQ_ERR_DEVICE or HQ_ERR_INVALID_ARG (tol <= 0 or NaN).
  * With Lambda = 0 the result is P(empty) = 1 and HQ_OK.
  */
@@ -205,15 +208,26 @@ hq_status hq_queue(const hq_ctx* ctx, double* summary, double* tail, int len);
  */
 hq_status hq_dispatch(const hq_ctx* ctx, const double* travel, double* q, double* mean_travel);
 
-/* Export P [2^N] (bitmask order, renormalised so that the whole system sums
- * to 1: with a waiting room the unit states sum to 1 - P(a call waits)) to
- * host memory.  HQ_ERR_STATE before any solve. */
+/*
+ * Export the stationary distribution of the last iterate, assembled as in
+ * Proposition 1 (Section 2.2): P(m) = p(|m|) p_|m|(m), with the number-busy
+ * marginal p(n) of (10) and the conditional layer probabilities p_n(m) of
+ * (8).  The final step of Algorithm 1.
+ *   P [2^N] caller-allocated host memory, bitmask order (bit u = unit u of
+ *     the caller's labels busy); renormalised so that the whole system sums
+ *     to 1 (with a waiting room the unit states sum to 1 - P(a call waits)).
+ * Stages the vector in a device buffer of 2^N doubles that the context
+ * allocates on the first export and keeps until hq_destroy (the buffer
+ * hq_dispatch uses).  Errors: HQ_ERR_INVALID_ARG (NULL), HQ_ERR_STATE
+ * before any solve, HQ_ERR_OUT_OF_MEMORY, HQ_ERR_DEVICE.
+ */
 hq_status hq_state(const hq_ctx* ctx, double* P);
 
 /*
  * Solve several instances (an uneven batch of candidate deployments) to tol
- * in one persistent launch (Section 3 iteration per instance, independent
- * instances).  Every context must be on the same device and must have been
+ * in one persistent launch: Algorithm 1 (initial iterate, Gauss-Seidel
+ * layer sweeps with the update (12)-(14), balance-residual stop on (1)) for
+ * every instance, the instances independent of each other.  Every context must be on the same device and must have been
  * created with HQ_FP64 or HQ_FP32 storage, the residual stopping rule and the
  * closed or one-update inner form (HQ_ERR_INVALID_ARG otherwise).  infos
  * (nullable) [count].
@@ -247,8 +261,9 @@ hq_status hq_reset(hq_ctx* ctx);
 /* Relative L1 balance residual of the current iterate, in FP64. */
 hq_status hq_residual(hq_ctx* ctx, double* residual);
 
-/* Conditional layer probabilities p_n(m) [2^N] in bitmask order
- * (unnormalised values as iterated; the resume format of HQ_INIT_STATE). */
+/* Conditional layer probabilities p_n(m) of (8) [2^N] in bitmask order
+ * (unnormalised values as iterated; the resume format of HQ_INIT_STATE).
+ * Stages through the same context-owned device buffer as hq_state. */
 hq_status hq_conditional(const hq_ctx* ctx, double* pcond);
 
 /* Layer scalars [4*(N+1)]: for n = 0..N, lambda(n), mu(n), p(n), and

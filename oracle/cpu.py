@@ -67,6 +67,9 @@ def lib():
         L.orc_birth_death.argtypes = [ctypes.c_int, d, d, ctypes.c_double, ctypes.c_double, ctypes.c_int, d, d, d]
         L.orc_dispatch.restype = None
         L.orc_dispatch.argtypes = [ctypes.c_int, ctypes.c_int, i32, d, d]
+        L.orc_time_sample.restype = ctypes.c_int
+        L.orc_time_sample.argtypes = [ctypes.c_int, ctypes.c_int, d, d, i32, ctypes.c_int, ctypes.c_longlong,
+                                      ctypes.c_longlong, ctypes.c_int, ctypes.c_int, d]
         L.orc_balance_terms.restype = None
         L.orc_balance_terms.argtypes = [ctypes.c_int, ctypes.c_int, d, d, i32, ctypes.c_longlong, u32, d, d, d]
         _lib = L
@@ -154,6 +157,20 @@ def solve(inst, *, tol: float = 1e-12, inner: str = "closed", delta: float = 1e-
         trace=None if trace is None else trace[:it].copy(),
         layer_trace=None if ltrace is None else ltrace[: it * (N + 1)].reshape(it, N + 1).copy(),
     )
+
+
+def time_sample(inst, n: int, first: int, count: int, reps: int, threads: int = 0) -> dict:
+    """Time Algorithm 1 on `count` consecutive states of layer n: step 2's
+    coefficient generation, then one outer-iteration update of those states
+    (same code as ``solve``).  Returns seconds of each and the threads used."""
+    lam, nu, pref = _args(inst)
+    out = np.zeros(4)
+    rc = lib().orc_time_sample(inst.N, inst.J, _dp(lam), _dp(nu), _ip(pref), int(n), int(first), int(count),
+                               int(reps), int(threads), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the timing sample")
+    return {"coef_s": float(out[0]), "update_s": float(out[1]), "threads": int(out[2]),
+            "checksum": float(out[3])}
 
 
 def residual(inst, P: np.ndarray, want_terms: bool = False):

@@ -165,6 +165,80 @@ static void free_layers(layers_t* L) {
 }
 
 /*
+ * Pieces of Algorithm 1 shared by orc_solve and the timing sample below.
+ *
+ * step2_coefficients: step 2 of Algorithm 1 (every coefficient once, by
+ * Algorithm 3) for `count` states (states[i], or i when states is NULL):
+ * mu[m] = mu_m and coef[m*N + u] = a(m, u).
+ */
+static void step2_coefficients(int N, int J, const double* lam, const double* nu, const int32_t* pref,
+                               const uint32_t* states, long long count, double* mu, double* coef) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (long long i = 0; i < count; ++i) {
+        uint32_t m = states ? states[i] : (uint32_t)i;
+        mu[m] = state_mu(N, nu, m);
+        orc_up_coefficients(N, J, lam, pref, m, coef + (size_t)m * N);
+    }
+}
+
+/* The two parts of (12) that do not depend on the inner iterate, for the
+ * states states[b..e) of one layer: U(m) = sum_{u in m} a(m,u) p(m\u) /
+ * (Lambda + mu_m) and D(m) = sum_{u notin m} nu_u p(m+u) / (Lambda + mu_m). */
+static void layer_parts(int N, const double* nu, double Lam, const double* coef, const double* mu,
+                        const double* p, const uint32_t* states, size_t b, size_t e, double* U, double* D) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (long long ii = (long long)b; ii < (long long)e; ++ii) {
+        uint32_t m = states[ii];
+        const double* a = coef + (size_t)m * N;
+        double up = 0.0, dn = 0.0;
+        for (int u = 0; u < N; ++u) {
+            uint32_t bit = 1u << u;
+            if (m & bit) up += a[u] * p[m ^ bit]; /* from layer n-1, lambda_lm */
+            else dn += nu[u] * p[m | bit];        /* from layer n+1, mu_lm = nu_u */
+        }
+        double den = Lam + mu[m]; /* lambda_m + mu_m, lambda_m = Lambda for n < N */
+        U[m] = up / den;
+        D[m] = dn / den;
+    }
+}
+
+/* One step of the inner loop: pnew(m) = ratio U(m) + beta D(m) over the
+ * layer; *change = max |pnew - previous pnew|; returns mu = sum mu_m pnew(m)
+ * (eq. (14)). */
+static double inner_step(const uint32_t* states, size_t b, size_t e, const double* U, const double* D,
+                         const double* mu, double ratio, double beta, double* pnew, double* change) {
+    double ch = 0.0, smu = 0.0;
+    for (size_t i = b; i < e; ++i) {
+        uint32_t m = states[i];
+        double v = ratio * U[m] + beta * D[m];
+        double d = fabs(v - pnew[m]);
+        if (d > ch) ch = d;
+        pnew[m] = v;
+        smu += mu[m] * v;
+    }
+    *change = ch;
+    return smu;
+}
+
+/* Commit a layer: p = pnew, the largest change, and the sums behind
+ * lambda(n) (13) and mu(n) (14). */
+static void commit_layer(const uint32_t* states, size_t b, size_t e, const double* pnew, const double* mu,
+                         double* p, double* maxdelta, double* sp, double* smu) {
+    double a = 0.0, c = 0.0, md = *maxdelta;
+    for (size_t i = b; i < e; ++i) {
+        uint32_t m = states[i];
+        double d = fabs(pnew[m] - p[m]);
+        if (d > md) md = d;
+        p[m] = pnew[m];
+        a += p[m];
+        c += mu[m] * p[m];
+    }
+    *maxdelta = md;
+    *sp = a;
+    *smu = c;
+}
+
+/*
  * Full Algorithm 1.
  *
  * Inputs: N (1..26), J >= 1, lam[J] >= 0 with sum > 0, nu[N] > 0,
@@ -222,12 +296,7 @@ int orc_solve(int N, int J, const double* lam, const double* nu, const int32_t* 
      * (step 2 of Algorithm 1 precomputes every coefficient once) */
     double* mu = (double*)malloc(sizeof(double) * S);
     double* coef = (double*)malloc(sizeof(double) * (size_t)S * N);
-#pragma omp parallel for schedule(dynamic, 256)
-    for (long long mm = 0; mm < (long long)S; ++mm) {
-        uint32_t m = (uint32_t)mm;
-        mu[m] = state_mu(N, nu, m);
-        orc_up_coefficients(N, J, lam, pref, m, coef + (size_t)m * N);
-    }
+    step2_coefficients(N, J, lam, nu, pref, NULL, (long long)S, mu, coef);
     clock_gettime(CLOCK_MONOTONIC, &t1);
 
     double* p = pcond;
@@ -269,20 +338,7 @@ int orc_solve(int N, int J, const double* lam, const double* nu, const int32_t* 
             const double Lprev = lamn[n - 1];            /* lambda^k(n-1), already updated */
             const double beta = lamn[n] / mun[n + 1];    /* lambda^{k-1}(n) / mu^{k-1}(n+1) */
             /* the two r-independent parts of (12) for every state of the layer */
-#pragma omp parallel for schedule(dynamic, 256)
-            for (long long ii = (long long)b; ii < (long long)e; ++ii) {
-                uint32_t m = LY.states[ii];
-                const double* a = coef + (size_t)m * N;
-                double up = 0.0, dn = 0.0;
-                for (int u = 0; u < N; ++u) {
-                    uint32_t bit = 1u << u;
-                    if (m & bit) up += a[u] * p[m ^ bit]; /* from layer n-1, lambda_lm */
-                    else dn += nu[u] * p[m | bit];        /* from layer n+1, mu_lm = nu_u */
-                }
-                double den = Lam + mu[m]; /* lambda_m + mu_m, lambda_m = Lambda for n < N */
-                U[m] = up / den;
-                D[m] = dn / den;
-            }
+            layer_parts(N, nu, Lam, coef, mu, p, LY.states, b, e, U, D);
             double mu_star;
             if (inner_mode == ORC_INNER_CLOSED) {
                 /* p(m) = (mu/Lprev) U(m) + beta D(m);  mu' = sum mu_m p(m) = A mu + B */
@@ -304,16 +360,8 @@ int orc_solve(int N, int J, const double* lam, const double* nu, const int32_t* 
                 double mu_cur = mun[n];
                 for (size_t i = b; i < e; ++i) pnew[LY.states[i]] = p[LY.states[i]];
                 for (int r = 0;; ++r) {
-                    double change = 0.0, smu = 0.0;
-                    for (size_t i = b; i < e; ++i) {
-                        uint32_t m = LY.states[i];
-                        double v = (mu_cur / Lprev) * U[m] + beta * D[m];
-                        double d = fabs(v - pnew[m]);
-                        if (d > change) change = d;
-                        pnew[m] = v;
-                        smu += mu[m] * v;
-                    }
-                    mu_cur = smu;
+                    double change = 0.0;
+                    mu_cur = inner_step(LY.states, b, e, U, D, mu, mu_cur / Lprev, beta, pnew, &change);
                     if (inner_mode == ORC_INNER_ONE) break;
                     if (change <= delta || r > 1000000) break;
                 }
@@ -322,14 +370,7 @@ int orc_solve(int N, int J, const double* lam, const double* nu, const int32_t* 
             (void)mu_star;
             /* commit the layer and its scalars (13)-(14) */
             double sp = 0.0, smu = 0.0;
-            for (size_t i = b; i < e; ++i) {
-                uint32_t m = LY.states[i];
-                double d = fabs(pnew[m] - p[m]);
-                if (d > maxdelta) maxdelta = d;
-                p[m] = pnew[m];
-                sp += p[m];
-                smu += mu[m] * p[m];
-            }
+            commit_layer(LY.states, b, e, pnew, mu, p, &maxdelta, &sp, &smu);
             lamn[n] = Lam * sp;
             mun[n] = smu;
         }
@@ -432,6 +473,86 @@ int orc_solve(int N, int J, const double* lam, const double* nu, const int32_t* 
     free(mun);
     free_layers(&LY);
     return converged ? 0 : 1;
+}
+
+/*
+ * Timing sample of Algorithm 1 (the CPU baseline of the benchmark), built
+ * from the same pieces as orc_solve: step 2's coefficients (Algorithm 3)
+ * for `count` consecutive states of layer n (colex order, starting at
+ * position `first`), then `reps` outer-iteration updates of those states
+ * with one inner step ((12), (14)) and the commit of (13)-(14), reading
+ * neighbours from full-size layers held at 1/C(N, n -+ 1).  `threads` > 0
+ * sets the OpenMP thread count for the call.
+ *   out[4]: seconds of the coefficient step, seconds per update rep,
+ *           threads used, a checksum of the updated values.
+ * Returns 0, or -1 on bad input or allocation failure.
+ */
+int orc_time_sample(int N, int J, const double* lam, const double* nu, const int32_t* pref, int n,
+                    long long first, long long count, int reps, int threads, double* out) {
+    if (N < 2 || N > 26 || n < 1 || n > N - 1 || first < 0 || count < 1 || reps < 1) return -1;
+    const uint32_t S = 1u << N;
+    const double layer_n = binom(N, n);
+    if ((double)(first + count) > layer_n) return -1;
+#ifdef _OPENMP
+    const int saved = omp_get_max_threads();
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    double Lam = 0.0;
+    for (int j = 0; j < J; ++j) Lam += lam[j];
+    /* the sample's states, in the order orc_solve visits layer n */
+    uint32_t* st = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)count);
+    double* mu = (double*)malloc(sizeof(double) * S);
+    double* coef = (double*)malloc(sizeof(double) * (size_t)S * N); /* only the sample's rows are touched */
+    double* p = (double*)malloc(sizeof(double) * S);
+    double* U = (double*)malloc(sizeof(double) * S);
+    double* D = (double*)malloc(sizeof(double) * S);
+    double* pnew = (double*)malloc(sizeof(double) * S);
+    int rc = 0;
+    if (!st || !mu || !coef || !p || !U || !D || !pnew) {
+        rc = -1;
+    } else {
+        long long pos = 0, k = 0;
+        for (uint32_t m = 0; m < S && k < count; ++m)
+            if (popcount32(m) == n) {
+                if (pos >= first) st[k++] = m;
+                ++pos;
+            }
+        double inv_c[33];
+        for (int i = 0; i <= N; ++i) inv_c[i] = 1.0 / binom(N, i);
+        for (uint32_t m = 0; m < S; ++m) p[m] = inv_c[popcount32(m)];
+        struct timespec t0, t1, t2;
+        clock_gettime(CLOCK_MONOTONIC, &t0);
+        step2_coefficients(N, J, lam, nu, pref, st, count, mu, coef);
+        clock_gettime(CLOCK_MONOTONIC, &t1);
+        /* any positive layer scalars: the cost does not depend on them */
+        const double ratio = 1.0 / Lam, beta = 1.0;
+        double maxdelta = 0.0, sp = 0.0, smu = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            double change = 0.0;
+            layer_parts(N, nu, Lam, coef, mu, p, st, 0, (size_t)count, U, D);
+            for (long long i = 0; i < count; ++i) pnew[st[i]] = p[st[i]];
+            (void)inner_step(st, 0, (size_t)count, U, D, mu, ratio, beta, pnew, &change);
+            commit_layer(st, 0, (size_t)count, pnew, mu, p, &maxdelta, &sp, &smu);
+        }
+        clock_gettime(CLOCK_MONOTONIC, &t2);
+        out[0] = (t1.tv_sec - t0.tv_sec) + 1e-9 * (t1.tv_nsec - t0.tv_nsec);
+        out[1] = ((t2.tv_sec - t1.tv_sec) + 1e-9 * (t2.tv_nsec - t1.tv_nsec)) / reps;
+        out[2] = orc_threads();
+        out[3] = sp + smu;
+    }
+    free(st);
+    free(mu);
+    free(coef);
+    free(p);
+    free(U);
+    free(D);
+    free(pnew);
+#ifdef _OPENMP
+    omp_set_num_threads(saved);
+#endif
+    return rc;
 }
 
 /*

@@ -22,6 +22,7 @@
 #include "hq_batchplan.h"
 #include "hq_init.h"
 #include "hq_layout.h"
+#include "hq_schedule.h"
 
 namespace hqk {
 hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
@@ -633,6 +634,7 @@ hq_status solve_impl(hq_ctx* c, double tol, hq_info* info) {
     const bool delta_stop = c->opts.stop == HQ_STOP_DELTA;
     const int prec = c->opts.precision;
     hq_status status = HQ_ERR_NOT_CONVERGED;
+    bool stalled64 = false;
     double sweep_ms = 0.0;
     try {
         run_init(c, prec != HQ_FP64);
@@ -653,9 +655,11 @@ hq_status solve_impl(hq_ctx* c, double tol, hq_info* info) {
                 inf.warm_used = 1;
             }
         }
-        int k = 0, next = fixed > 0 ? fixed : std::min(8, max_iters);
-        double last_res = -1.0, prev_res = -1.0;
-        int prev_k = 0, stall = 0, fp64_from = prec == HQ_FP64 ? 0 : -1;
+        // residual-check schedule and stall detection (hq_schedule.h)
+        hqsched::Tracker tr = hqsched::start();
+        int k = 0, next = fixed > 0 ? fixed : std::min(hqsched::kFirstCheck, max_iters);
+        double last_res = -1.0;
+        int stall32 = 0, fp64_from = prec == HQ_FP64 ? 0 : -1;
         double misc[3] = {0, 0, 0};
         while (k < max_iters) {
             HQ_HIP(hipEventRecord(c->ev0, c->stream));
@@ -690,7 +694,7 @@ hq_status solve_impl(hq_ctx* c, double tol, hq_info* info) {
                 last_res = res;
                 break;
             }
-            prev_res = last_res;
+            const double prev_res = tr.prev_res;
             last_res = res;
             if (res <= tol) {
                 status = HQ_OK;
@@ -703,31 +707,25 @@ hq_status solve_impl(hq_ctx* c, double tol, hq_info* info) {
                     if (prec == HQ_FP32_POLISH64) {
                         widen(c);
                         fp64_from = k;
-                        prev_res = -1.0;
-                        last_res = -1.0;
+                        tr = hqsched::start();
+                        tr.prev_k = k;
                         next = k + (fixed > 0 ? fixed : 4);
-                        prev_k = k;
                         continue;
                     }
-                    if (stalled && ++stall >= 3) {
+                    if (stalled && ++stall32 >= 3) {
                         status = HQ_ERR_NOT_CONVERGED;
                         break;
                     }
                 }
             }
-            // schedule the next check: extrapolate the geometric decay
-            if (fixed > 0) {
-                next = k + fixed;
-            } else if (prev_res > 0.0 && res < prev_res) {
-                const double rate = std::pow(res / prev_res, 1.0 / std::max(1, k - prev_k));
-                const double need = std::log(tol / res) / std::log(rate);
-                int step = (int)std::ceil(need);
-                step = std::max(1, std::min(step, 64));
-                next = k + step;
-            } else {
-                next = k + 8;
+            // schedule the next check (extrapolated decay); an FP64 iterate
+            // whose residual has stopped falling ends the solve
+            next = hqsched::next_check(tr, k, res, tol, fixed);
+            if (hqsched::record(tr, k, res) && !c->active_fp32) {
+                status = HQ_ERR_NOT_CONVERGED;
+                stalled64 = true;
+                break;
             }
-            prev_k = k;
         }
         inf.iterations = k;
         inf.fp64_iterations = fp64_from >= 0 ? k - fp64_from : 0;
@@ -750,7 +748,9 @@ hq_status solve_impl(hq_ctx* c, double tol, hq_info* info) {
     inf.state_updates_per_s = inf.sweep_seconds > 0 ? (double)(c->states() - 2) * inf.iterations / inf.sweep_seconds : 0.0;
     inf.status = status;
     if (info) *info = inf;
-    if (status == HQ_ERR_NOT_CONVERGED) g_err = "max_iters reached (or FP32 floor) before tol";
+    if (status == HQ_ERR_NOT_CONVERGED)
+        g_err = stalled64 ? "the residual stopped decreasing before tol (rounding floor or divergence)"
+                          : "max_iters reached (or FP32 floor) before tol";
     if (status == HQ_ERR_NUMERIC) g_err = "non-finite value or zero denominator in a layer reduction";
     return status;
 }
@@ -1133,19 +1133,20 @@ static hq_status host_export(const hq_ctx* c, double* out, int conditional) {
         out[0] = 1.0;
         return HQ_OK;
     }
-    double* tmp = nullptr;
+    hq_ctx* cm = const_cast<hq_ctx*>(c);
     try {
-        tmp = dalloc<double>(S);
-        export_impl(c, tmp, conditional, c->stream);
-        HQ_HIP(hipMemcpyAsync(out, tmp, S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        // the staging vector in bitmask order is the context's (the same
+        // buffer as the dispatch transform's), allocated on first use and
+        // kept until hq_destroy
+        if (!cm->d_G) cm->d_G = dalloc<double>(S);
+        export_impl(c, cm->d_G, conditional, c->stream);
+        HQ_HIP(hipMemcpyAsync(out, cm->d_G, S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HQ_HIP(hipStreamSynchronize(c->stream));
     } catch (const std::bad_alloc&) {
         return fail(HQ_ERR_OUT_OF_MEMORY, "device allocation failed");
     } catch (const HipError& e) {
-        if (tmp) (void)hipFree(tmp);
         return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
     }
-    (void)hipFree(tmp);
     return HQ_OK;
 }
 

@@ -27,6 +27,7 @@
 // work-group to finish, which also derives the layer scalars.
 #include "hq_internal.h"
 #include "hq_layout.h"
+#include "hq_schedule.h"
 
 #include <math.h>
 
@@ -1023,9 +1024,11 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
             }
         }
         __syncthreads();
-        int k = 0, checks = 0, status = HQ_ERR_NOT_CONVERGED_CODE, next_check = B.check_every > 0 ? B.check_every : 8;
-        double res = -1.0, prev_res = -1.0;
-        int prev_k = 0, stall = 0;
+        int k = 0, checks = 0, status = HQ_ERR_NOT_CONVERGED_CODE;
+        int next_check = B.check_every > 0 ? B.check_every : hqsched::kFirstCheck;
+        double res = -1.0;
+        hqsched::Tracker tr = hqsched::start();  // used by thread 0 only
+        int stall32 = 0;
         if (next_check > B.max_iters) next_check = B.max_iters;
         while (k < B.max_iters) {
             for (int n = 1; n <= N - 1; ++n) {
@@ -1078,20 +1081,12 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
                     status = 0;
                     go = 0;
                 } else {
-                    if (sizeof(T) == 4 && prev_res > 0.0 && res > 0.8 * prev_res && ++stall >= 3) go = 0;
-                    if (B.check_every > 0) {
-                        next_check = k + B.check_every;
-                    } else if (prev_res > 0.0 && res < prev_res) {
-                        const double rate = pow(res / prev_res, 1.0 / (double)max(1, k - prev_k));
-                        int step = (int)ceil(log(B.tol / res) / log(rate));
-                        next_check = k + max(1, min(step, 64));
-                    } else {
-                        next_check = k + 8;
-                    }
+                    // FP32 storage floor, or an FP64 residual that stopped falling
+                    if (sizeof(T) == 4 && tr.prev_res > 0.0 && res > 0.8 * tr.prev_res && ++stall32 >= 3) go = 0;
+                    next_check = hqsched::next_check(tr, k, res, B.tol, B.check_every);
+                    if (hqsched::record(tr, k, res) && sizeof(T) == 8) go = 0;
                     if (next_check > B.max_iters) next_check = B.max_iters;
                 }
-                prev_res = res;
-                prev_k = k;
                 s_go = go;
                 s_next = next_check;
             }

@@ -1,7 +1,7 @@
 // Learned warm start: a small MLP predicting per-unit utilisations, trained
 // and evaluated on the GPU with hand-written BF16 MFMA kernels (gfx950).
 //
-// Network: x[16] -> relu(x W1 + b1)[256] -> relu(h1 W2 + b2)[256]
+// Network: x[32] -> relu(x W1 + b1)[256] -> relu(h1 W2 + b2)[256]
 //          -> sigmoid(h2 . w3 + b3) = predicted busy probability of a unit.
 // Weights are kept in FP32 (master copy, Adam state) and cast to BF16 for
 // the matrix products; products accumulate in FP32 on the matrix cores.

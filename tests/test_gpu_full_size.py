@@ -55,6 +55,20 @@ def test_full_size_layer_update(big):
     _layer_update_parity(*big)
 
 
+@pytest.mark.parametrize("inner", ["closed", "literal"])
+def test_full_size_layer_update_inner_forms(big, inner):
+    # the first-pass kernels of the closed and literal inner forms at the
+    # benchmark's tile shape (b = 10, H = 16), with alpha_n rebuilt on the
+    # host from the oracle's layer sums
+    _layer_update_parity(*big, inner=inner, layers=(1, 3, 9, 13, 24, 25))
+
+
+def test_full_size_layer_update_fp32(big):
+    # FP32 storage with per-layer scales at the benchmark's tile shape: the
+    # stored value is the FP64 update rounded once to FP32
+    _layer_update_parity(*big, precision="fp32", rtol=1.2e-7)
+
+
 @pytest.mark.parametrize("N,tile_bits", [(27, 0), (28, 0), (28, 12)])
 def test_larger_tile_shapes_layer_update(N, tile_bits):
     # default 10-bit tiles: the b = 10, H = 17 and H = 18 kernels; and the
@@ -64,14 +78,44 @@ def test_larger_tile_shapes_layer_update(N, tile_bits):
     _layer_update_parity(inst, *_tables(inst), tile_bits=tile_bits)
 
 
-def _layer_update_parity(inst, pop, mu_m, tile_bits=0):
+def _layer_states(N, n):
+    m = np.arange(1 << N, dtype=np.uint32)
+    return m[np.bitwise_count(m) == n]
+
+
+def _literal_alpha(inst, n, S_low, S_up, S_prev, alpha0, beta, L, delta, mu_m):
+    """alpha_n of the literal inner loop of Algorithm 1 with tolerance delta:
+    p^r = (mu_r / L) U~ + beta D~, mu_{r+1} = sum mu_m p^r, from
+    mu_0 = mu^{k-1}(n), until the largest change of a step is <= delta
+    (the first step is compared with the previous iterate).  U~, D~ of every
+    state of the layer come from the oracle."""
+    st = _layer_states(inst.N, n)
+    _, U, D = cpu.update_states(inst, st, S_low, S_up, 0.0, 0.0)
+    mu = mu_m[st]
+    mu_r = alpha0 * L
+    p = (mu_r / L) * U + beta * D
+    change = np.abs(p - S_prev[st]).max()
+    while not change <= delta:
+        mu_next = float((mu * p).sum())
+        p_next = (mu_next / L) * U + beta * D
+        change = np.abs(p_next - p).max()
+        mu_r, p = mu_next, p_next
+    return mu_r / L
+
+
+def _layer_update_parity(inst, pop, mu_m, tile_bits=0, inner="one", precision="fp64", rtol=1e-11,
+                         layers=None):
     N, Lam = inst.N, inst.Lambda
-    say(f"case N={N} layer update: iterate")
-    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE, tile_bits=tile_bits)
+    delta = 1e-6
+    say(f"case N={N} layer update ({inner}, {precision}): iterate")
+    inner_code = {"one": hq.HQ_INNER_ONE, "closed": hq.HQ_INNER_CLOSED, "literal": hq.HQ_INNER_LITERAL}[inner]
+    prec = hq.HQ_FP32 if precision == "fp32" else hq.HQ_FP64
+    ctx = hq.create_from_instance(inst, inner=inner_code, tile_bits=tile_bits, precision=prec, delta=delta)
     hq.hq_iterate(ctx, 2)
     S1 = hq.hq_conditional(ctx)
     hq.hq_iterate(ctx, 1)
     S2 = hq.hq_conditional(ctx)
+    hq.hq_destroy(ctx)
     rng = np.random.default_rng(0)
 
     def lam_of(S, n):
@@ -80,15 +124,22 @@ def _layer_update_parity(inst, pop, mu_m, tile_bits=0):
     def mu_of(S, n):
         return float((mu_m[pop == n] * S[pop == n]).sum())
 
-    for n in (1, 3, 9, N // 2, N - 9, N - 6, N - 2, N - 1):
+    for n in layers or (1, 3, 9, N // 2, N - 9, N - 6, N - 2, N - 1):
         say(f"case N={N} layer {n}")
-        alpha = mu_of(S1, n) / lam_of(S2, n - 1)  # mu^2(n) / lambda^3(n-1)
+        L = lam_of(S2, n - 1)                     # lambda^3(n-1)
         beta = lam_of(S1, n) / mu_of(S1, n + 1)   # lambda^2(n) / mu^2(n+1)
+        alpha = mu_of(S1, n) / L                  # one inner update: mu^2(n) / lambda^3(n-1)
+        if inner == "closed":
+            sums = cpu.layer_sums(inst, n, S2, S1)
+            alpha = cpu.closed_form_alpha(L, beta, sums)
+        elif inner == "literal":
+            alpha = _literal_alpha(inst, n, S2, S1, S1, alpha, beta, L, delta, mu_m)
         states = _sample_layer(rng, N, n, 1500)
         want, _, _ = cpu.update_states(inst, states, S2, S1, alpha, beta)
         got = S2[states]
         rel = np.abs(got - want) / np.abs(want)
-        assert rel.max() <= 1e-11, (n, rel.max())
+        say(f"  max relative error {rel.max():.2e}")
+        assert rel.max() <= rtol, (n, rel.max())
 
 
 def test_maximum_size_layer_update():

@@ -492,6 +492,41 @@ def test_dispatch_ordered_hunting_closed_form():
         np.testing.assert_allclose(q[:, row[h]], B[h] - B[h + 1], rtol=1e-10)
 
 
+def test_golden_hand_derived_n2_dispatch_and_travel():
+    """Dispatch rule of eq. (3) and the mean travel time, by hand on the
+    2-unit system: per-node dispatch probabilities and a non-constant
+    travel-time matrix (a weighting by q alone would give 452/172)."""
+    g = _read_golden("n2_hand.txt")
+    inst = _inst(int(g["N"][0]), int(g["J"][0]), [float(x) for x in g["lam"]],
+                 [float(x) for x in g["nu"]], g["pref"])
+    den = float(g["P_den"][0])
+    P = np.array([int(x) for x in g["P_num"]], float) / den
+    q = cpu.dispatch(inst, P)
+    want_q = np.array([int(x) for x in g["q_num"]], float).reshape(2, 2) / den
+    np.testing.assert_allclose(q, want_q, rtol=0, atol=1e-15)
+    t = np.array([float(x) for x in g["travel"]]).reshape(2, 2)
+    want = float(g["mean_travel_num"][0]) / float(g["mean_travel_den"][0])
+    assert cpu.mean_travel(inst, q, t) == pytest.approx(want, rel=1e-14)
+
+
+def test_mean_travel_unit_indicator_is_flow_share():
+    """With t = 1 for unit u and 0 elsewhere, the mean travel time is the
+    share of dispatched calls that unit u serves: nu_u rho_u over
+    Lambda (1 - P(full)) (flow balance of unit u in the stationary law).
+    A weighting by q alone, or by lambda alone, fails this."""
+    inst = config_instance(1, 9, N=6, J=10)
+    P = exact.dense_solve(inst)
+    q = cpu.dispatch(inst, P)
+    m = np.arange(1 << inst.N)
+    Lam = float(np.sum(inst.lam))
+    for u in range(inst.N):
+        rho_u = P[(m >> u) & 1 == 1].sum()
+        t = np.zeros((inst.J, inst.N))
+        t[:, u] = 1.0
+        want = inst.nu[u] * rho_u / (Lam * (1.0 - P[-1]))
+        assert cpu.mean_travel(inst, q, t) == pytest.approx(want, rel=1e-10)
+
+
 def test_mean_travel_definition():
     inst = config_instance(1, 9, N=6, J=10)
     P = exact.dense_solve(inst)
