@@ -15,7 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["hq_kernels.hip", "hq_api.cpp", "hq_mlp.hip", "hq_mlp_api.cpp"]
+SOURCES = ["hq_kernels.hip", "hq_sweep.hip", "hq_api.cpp", "hq_mlp.hip", "hq_mlp_api.cpp"]
 OUT = os.path.join(HERE, "libhq.so")
 OBJDIR = os.path.join(HERE, "_build")
 

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -23,6 +24,7 @@
 #include "hq_init.h"
 #include "hq_layout.h"
 #include "hq_schedule.h"
+#include "hq_sweeptab.h"
 
 namespace hqk {
 hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
@@ -137,6 +139,9 @@ struct hq_ctx {
     uint16_t *d_lo_unrank = nullptr, *d_lo_rank = nullptr;
     TrieNode* d_nodes = nullptr;
     unsigned int* d_counters = nullptr;
+    uint32_t* d_srec = nullptr;  // segment records of the default-shape sweep
+    LowRow* d_lrow = nullptr;    // its low-pattern rows (FP64 offsets)
+    LowRow* d_lrow32 = nullptr;  // and with FP32 offsets
     SweepParams P64{}, P32{};
     bool have_iterate = false;
     bool learned = false;      // product-form weights came from the network
@@ -149,7 +154,8 @@ struct hq_ctx {
                         d_scale64, d_scale32,  d_rho,      d_xu,       d_given,     d_binom,    d_layer_off,
                         d_lo_qstart, d_prog_off, d_prog, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
                         d_counters, d_seg_desc, d_segoff,   d_coefs,     d_seg_prog, d_G,
-                        d_q,       d_lam_in,   d_travel,   d_tsum,     d_pref_in};
+                        d_q,       d_lam_in,   d_travel,   d_tsum,     d_pref_in,  d_srec,      d_lrow,
+                        d_lrow32};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         x64 = nullptr;
@@ -269,6 +275,9 @@ void setup_params(hq_ctx* c) {
     P.sc.rden = c->d_scal + 5 * L;
     P.sc.delta = c->d_scal + 6 * L;
     P.sc.misc = c->d_scal + 7 * L;
+    P.srec = c->d_srec;
+    P.lrow = c->d_lrow;
+    P.lrow32 = c->d_lrow32;
     P.partials = c->d_part;
     P.counters = c->d_counters;
     c->P64 = P;
@@ -391,6 +400,17 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         seg_prog[2 * i] = prog_off[T * (N + 1)];
         seg_prog[2 * i + 1] = prog_off[T * (N + 1) + N] - prog_off[T * (N + 1)];
     }
+    // segment records and low-pattern rows of the default-shape sweep
+    // (hq_sweep.hip); HQ_LEGACY_SWEEP=1 in the environment keeps every
+    // layer on the general kernels instead
+    std::vector<uint32_t> srec;
+    std::vector<LowRow> lrow, lrow32;
+    const char* legacy = std::getenv("HQ_LEGACY_SWEEP");
+    if (b == HQ_SWEEP_B && c->H >= 6 && c->H <= 20 && !(legacy && legacy[0] == '1')) {
+        lrow = hqsweeptab::low_rows(lay, c->nu, 8);
+        lrow32 = hqsweeptab::low_rows(lay, c->nu, 4);
+        srec = hqsweeptab::seg_records(lay, prog_off, c->nu);
+    }
     c->layers.resize(N + 1);
     size_t max_groups = 1;
     for (int n = 0; n <= N; ++n) {
@@ -497,6 +517,11 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->d_lo_rank = dalloc<uint16_t>(lo_rank.size());
         c->d_nodes = dalloc<TrieNode>(c->nodes.size());
         c->d_counters = dalloc<unsigned int>(N + 1);
+        if (!srec.empty()) {
+            c->d_srec = dalloc<uint32_t>(srec.size());
+            c->d_lrow = dalloc<LowRow>(lrow.size());
+            c->d_lrow32 = dalloc<LowRow>(lrow32.size());
+        }
         hipStream_t s = c->stream;
         h2d(c->d_nu, c->nu, s);
         h2d(c->d_mu_lo, mu_lo, s);
@@ -515,6 +540,11 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         h2d(c->d_lo_unrank, lo_unrank, s);
         h2d(c->d_lo_rank, lo_rank, s);
         h2d(c->d_nodes, c->nodes, s);
+        if (!srec.empty()) {
+            h2d(c->d_srec, srec, s);
+            h2d(c->d_lrow, lrow, s);
+            h2d(c->d_lrow32, lrow32, s);
+        }
         HQ_HIP(hipMemsetAsync(c->d_counters, 0, sizeof(unsigned int) * (N + 1), s));
         HQ_HIP(hipMemsetAsync(c->d_scal, 0, sizeof(double) * (8 * (N + 1) + 8), s));
         if (!c->state_init.empty()) {

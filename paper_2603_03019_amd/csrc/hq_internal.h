@@ -5,7 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "hq_tables.h"  // ProgTerm
+#include "hq_sweeptab.h"  // LowRow, segment record layout
+#include "hq_tables.h"    // ProgTerm
 
 #define HQ_MAXB 12          // largest low-bit tile width b
 #define HQ_MAXH 26          // largest high-bit count H = N - b
@@ -70,6 +71,9 @@ struct SweepParams {
     const double* scale;         // [N+1] storage scale of each layer (x = scale * p)
     const double* inv_scale;     // [N+1]
     DevScalars sc;
+    const uint32_t* srec;        // segment records (HQ_REC_WORDS each), seg_desc order; b = HQ_SWEEP_B only
+    const LowRow* lrow;          // [2^b] low-pattern rows, FP64 offsets; b = HQ_SWEEP_B only
+    const LowRow* lrow32;        // the same with FP32 offsets
     double* partials;            // [max_groups * 32]
     unsigned int* counters;      // [N+1]
 };

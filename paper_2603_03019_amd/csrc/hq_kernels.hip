@@ -1285,8 +1285,17 @@ static void launch_layer_s(int mode, bool track_delta, const SweepParams& P, con
         hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
 }
 
+uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
+                      int inner_one, hipStream_t s);
+
 hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A,
                         void* x, int inner_one, hipStream_t s) {
+    // the default tile shape runs on the sweep kernels of hq_sweep.hip
+    const uint32_t parts = launch_sweep(mode, track_delta, fp32, P, A, x, inner_one, s);
+    if (parts) {
+        hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(HQ_WG), 0, s, P, mode, A.n, parts, inner_one);
+        return hipGetLastError();
+    }
     if (fp32) {
         if (A.stored)
             launch_layer_s<float, true>(mode, track_delta, P, A, (float*)x, inner_one, s);

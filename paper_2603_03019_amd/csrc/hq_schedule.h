@@ -8,9 +8,10 @@
 // rate predicts the tolerance will be met (at most 64 iterations ahead).  A
 // check that shows no decrease is followed by one 8 iterations later.
 //
-// A solve has stalled when several checks in a row show (almost) no
-// decrease: below a factor 0.9999 per outer iteration.  That happens at the
-// rounding floor of the arithmetic (a tolerance below what FP64 can reach)
+// A solve has stalled when several checks in a row fail to improve on the
+// best residual seen so far by at least a factor 0.9999 per outer iteration
+// since that best.  That happens at the rounding floor of the arithmetic (a
+// tolerance below what FP64 can reach), where the residual only fluctuates,
 // or when the iterate diverges; the caller then returns
 // HQ_ERR_NOT_CONVERGED with the residual reached instead of running to
 // max_iters.
@@ -35,17 +36,20 @@ constexpr int kStallChecks = 6;       // checks in a row without progress that e
 struct Tracker {
     double prev_res;  // residual at the previous check (< 0: none yet)
     int prev_k;       // iteration of the previous check
+    double best;      // best residual that counted as progress (< 0: none yet)
+    int best_k;       // its iteration
     int stall;        // checks in a row without progress
 };
 
-HQ_SD Tracker start() { return Tracker{-1.0, 0, 0}; }
+HQ_SD Tracker start() { return Tracker{-1.0, 0, -1.0, 0, 0}; }
 
-// Whether the check at iteration k (residual res) fell short of progress
-// against the previous one.  A NaN residual counts as no progress.
+// Whether the check at iteration k (residual res) fell short of progress:
+// not below the best residual so far by kProgress per iteration since it.
+// A NaN residual counts as no progress.
 HQ_SD bool no_progress(const Tracker& t, int k, double res) {
-    if (!(t.prev_res > 0.0)) return false;
-    const int dk = k - t.prev_k > 1 ? k - t.prev_k : 1;
-    return !(res <= t.prev_res * pow(kProgress, (double)dk));
+    if (!(t.best > 0.0)) return false;
+    const int dk = k - t.best_k > 1 ? k - t.best_k : 1;
+    return !(res <= t.best * pow(kProgress, (double)dk));
 }
 
 // Iteration of the next check after the one at iteration k.  fixed > 0: a
@@ -69,7 +73,13 @@ HQ_SD int next_check(const Tracker& t, int k, double res, double tol, int fixed)
 // Record the check at iteration k; true once kStallChecks checks in a row
 // have shown no progress.
 HQ_SD bool record(Tracker& t, int k, double res) {
-    t.stall = no_progress(t, k, res) ? t.stall + 1 : 0;
+    if (no_progress(t, k, res)) {
+        t.stall += 1;
+    } else {
+        t.stall = 0;
+        t.best = res;
+        t.best_k = k;
+    }
     t.prev_res = res;
     t.prev_k = k;
     return t.stall >= kStallChecks;

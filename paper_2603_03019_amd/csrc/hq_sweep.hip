@@ -1,0 +1,436 @@
+// The layer sweep for the default tile shape (b = 10 low bits per tile,
+// H = N - 10 high bits, N = 16..30): one kernel per layer launch that
+// evaluates, for every state m of layer n, the two gathers of the update
+// (12) of Algorithm 1,
+//     U~(m) = sum_{u in m}    a(m, u) p_{n-1}(m \ u) / (Lambda + mu_m),
+//     D~(m) = sum_{u notin m} nu_u    p_{n+1}(m + u) / (Lambda + mu_m),
+// and then writes p_n(m) = alpha_n U~ + beta_n D~ (sweep), reduces the
+// layer sums of the inner mu(n) loop (first pass of the closed and literal
+// forms), or evaluates the balance residual of (1) (check).
+//
+// Mapping.  A 64-lane wave owns one segment (tile T, low class q) at a time:
+// the C(10, q) states that share their high bits, lane t taking states t,
+// t + 64, ...  What is uniform over the segment comes from a precomputed
+// 128-byte record (neighbour segment starts, the tile's program position,
+// the service-rate sum of the busy high units), fetched lane-parallel two
+// segments ahead.  What depends on the low pattern comes from a 40-byte row
+// per (q, t), read coalesced: for the pattern's q set bits (increasing) the
+// offset of the neighbour L minus that bit inside segment (T, q - 1) of layer
+// n - 1, then for its 10 - q clear bits the offset of L plus that bit inside
+// (T, q + 1) of layer n + 1, each with the LDS slot of its weight, and the
+// service-rate sum of the pattern's units.  So entry i is a down-neighbour
+// for every lane iff i < q: no per-lane branch.  High-bit neighbours sit at
+// the same offset t of segment (T xor 2^k, q) and are read as contiguous
+// runs.  Every load and store goes through one buffer resource spanning
+// layers n - 1 .. n + 1, with the segment starts as scalar offsets.
+//
+// Weights.  Per segment, lane u forms the weight of unit u in the combined
+// sum: alpha-side (tile coefficient of a busy unit, eq. (3) / Algorithm 3)
+// or beta-side (service rate of an idle unit), with the layer scalars and
+// storage scales folded in.  High units' weights are broadcast to scalar
+// registers; low units' weights go to a per-wave LDS slot and are read by
+// the lane's entry.  Per-tile program terms (busy units whose coefficient
+// depends on low bits) are added for the units the record marks.
+//
+// Arithmetic is FP64 throughout; with FP32 storage the neighbour values are
+// widened on load and the written value rounded once.
+#include "hq_internal.h"
+
+#include <math.h>
+
+namespace hqsweep {
+
+#define HQ_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const HQ_CONST T* cro(const T* p) {
+    return (const HQ_CONST T*)p;
+}
+
+constexpr int B = HQ_SWEEP_B;  // low bits per tile
+constexpr int WAVES = HQ_WG / 64;
+constexpr int RSRC_W3 = 0x00020000;  // buffer resource word 3 on gfx9 (32-bit data format, raw)
+
+enum { S_WRITE = 0, S_PASS1 = 1, S_RESID = 2 };
+
+__device__ __forceinline__ uint32_t rl(uint32_t v, int i) { return (uint32_t)__builtin_amdgcn_readlane((int)v, i); }
+__device__ __forceinline__ double rld(double v, int i) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = rl((uint32_t)b, i), hi = rl((uint32_t)(b >> 32), i);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+
+// 1 / d for d > 0: the hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+template <typename T>
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, T v, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
+
+// Layer scalars of one launch.  wa/wb: factors of the alpha-side (busy
+// unit, tile coefficient) and beta-side (idle unit, service rate) weights.
+struct Scal {
+    double wa, wb;            // S_WRITE: alpha s_self / s_dn, beta s_self / s_up; S_RESID: p(n-1) / s_dn,
+                              // p(n+1) / s_up; S_PASS1: 1 / s_dn, 1 / s_up (two sums)
+    double alpha0, beta0;     // literal loop: first inner step
+    double is_self, pself;    // inverse storage scale of layer n; p(n) (residual)
+};
+
+template <int MODE>
+__device__ __forceinline__ Scal load_scal(const SweepParams& P, int n, int inner_one) {
+    Scal s{};
+    const int N = P.N;
+    const double is_dn = P.inv_scale[n - 1], is_up = P.inv_scale[n + 1];
+    s.is_self = P.inv_scale[n];
+    if (MODE == S_RESID) {
+        s.wa = P.sc.pn[n - 1] * is_dn;
+        s.wb = P.sc.pn[n + 1] * is_up;
+        s.pself = P.sc.pn[n];
+    } else {
+        const double beta = P.sc.lam[n] / P.sc.mu[n + 1];    // lambda^{k-1}(n) / mu^{k-1}(n+1)
+        const double alpha0 = P.sc.mu[n] / P.sc.lam[n - 1];  // mu^{k-1}(n) / lambda^k(n-1)
+        s.alpha0 = alpha0;
+        s.beta0 = beta;
+        if (MODE == S_WRITE) {
+            const double alpha = inner_one == 1 ? alpha0 : P.sc.alpha[n];
+            const double s_self = P.scale[n];
+            s.wa = alpha * is_dn * s_self;
+            s.wb = beta * is_up * s_self;
+        } else {
+            s.wa = is_dn;
+            s.wb = is_up;
+        }
+    }
+    (void)N;
+    return s;
+}
+
+// One wave, one segment.  HF = H (high bits), fixed at compile time.
+template <typename T, int MODE, bool TRACK, int HF>
+__device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rsrc_t xr,
+                                        __amdgpu_buffer_rsrc_t rowr, const uint32_t base, const uint32_t rec,
+                                        const double tcv, const uint32_t pov, const Scal& s, double* wlds,
+                                        const uint16_t* s_rank, double& acc0, double& acc1, double& acc2,
+                                        double& acc3) {
+    constexpr uint32_t SZ = sizeof(T);
+    const int lane = threadIdx.x & 63;
+    const uint32_t desc = rl(rec, HQ_REC_DESC);
+    const int q = (int)(desc & 15u);
+    const uint32_t Tb = desc >> 4;
+    // scalar byte offsets inside the window (layers n-1 .. n+1)
+    const uint32_t o_self = (rl(rec, HQ_REC_SELF) - base) * SZ;
+    // (a segment without down- or up-neighbour segment gets offset 0, the
+    // window's first element, which no lane then reads)
+    const uint32_t o_dn = q > 0 ? (rl(rec, HQ_REC_DN) - base) * SZ : 0u;
+    const uint32_t o_up = q < B ? (rl(rec, HQ_REC_UP) - base) * SZ : 0u;
+    uint32_t o_hi[HF];
+#pragma unroll
+    for (int k = 0; k < HF; ++k) o_hi[k] = (rl(rec, HQ_REC_HI + k) - base) * SZ;
+    const double mu_hi = __longlong_as_double(
+        (long long)(((unsigned long long)rl(rec, HQ_REC_MUHI + 1) << 32) | rl(rec, HQ_REC_MUHI)));
+    const double den_hi = P.Lam + mu_hi;
+    const uint32_t cnt = cro(P.binom)[B * 32 + q];
+    const uint32_t qs = cro(P.lo_qstart)[q];
+    const uint32_t pmask = rl(rec, HQ_REC_PMASK);
+    // weights: lane u < N holds unit u's; alpha-side for busy units (tile
+    // coefficient), beta-side for idle ones (service rate)
+    const double nu_l = lane < P.N ? cro(P.nu)[lane] : 0.0;
+    const bool busy_hi = lane >= B && lane < P.N && ((Tb >> (lane - B)) & 1u);
+    double wA = 0.0, wB = 0.0;  // PASS1 keeps the two sides apart (side factors applied at the end)
+    if (MODE == S_PASS1) {
+        wA = busy_hi ? tcv : 0.0;
+        wB = busy_hi ? 0.0 : nu_l;
+    } else {
+        wA = busy_hi ? s.wa * tcv : s.wb * nu_l;
+    }
+    // the weights into this wave's LDS slots: low unit l busy at [l], idle
+    // at [16 + l]; high unit B + k at [32 + k] (PASS1: busy side there and
+    // idle side at [48 + k]; the side factors are applied at the end)
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < B) {
+        wlds[lane] = MODE == S_PASS1 ? tcv : s.wa * tcv;
+        wlds[16 + lane] = MODE == S_PASS1 ? nu_l : s.wb * nu_l;
+    } else if (lane < P.N) {
+        wlds[32 + lane - B] = wA;
+        if (MODE == S_PASS1) wlds[48 + lane - B] = wB;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+
+    for (uint32_t t = lane; t < cnt; t += 64) {
+        // weights are read from LDS in every pass (kept out of registers)
+        asm volatile("" ::: "memory");
+        const uint32_t ro = (qs + t) * (uint32_t)sizeof(LowRow);
+        // row: L | off[10] | slot[10] | mu_lo
+        const auto r0 = __builtin_amdgcn_raw_buffer_load_b128(rowr, ro, 0, 0);
+        const auto r1 = __builtin_amdgcn_raw_buffer_load_b128(rowr, ro + 16, 0, 0);
+        const double mu_lo = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rowr, ro + 32, 0, 0));
+        const uint32_t w[8] = {r0[0], r0[1], r0[2], r0[3], r1[0], r1[1], r1[2], r1[3]};
+        const uint32_t L = w[0] & 0xffffu;
+        const uint32_t t8 = t * SZ;
+        // every neighbour value first
+        double vl[B], vh[HF];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            // off[i] is the 16-bit field at byte 2 + 2 i
+            const uint32_t word = w[(2 + 2 * i) >> 2];
+            const uint32_t off = ((2 + 2 * i) & 3) ? (word >> 16) : (word & 0xffffu);
+            vl[i] = bload<T>(xr, off, i < q ? o_dn : o_up);
+        }
+#pragma unroll
+        for (int k = 0; k < HF; ++k) vh[k] = bload<T>(xr, t8, o_hi[k]);
+        double A = 0.0, Bs = 0.0;
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            // slot[i] is the byte at 22 + i
+            const uint32_t word = w[(22 + i) >> 2];
+            const uint32_t slot = (word >> (8 * ((22 + i) & 3))) & 0xffu;
+            const double wl = *(const double*)((const char*)wlds + slot);
+            if (MODE == S_PASS1) {
+                if (i < q)
+                    A = fma(wl, vl[i], A);
+                else
+                    Bs = fma(wl, vl[i], Bs);
+            } else {
+                A = fma(wl, vl[i], A);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < HF; ++k) {
+            A = fma(wlds[32 + k], vh[k], A);
+            if (MODE == S_PASS1) Bs = fma(wlds[48 + k], vh[k], Bs);
+        }
+        // per-tile program terms: a busy unit u gains `rate` in the states
+        // whose low bits contain the term's mask
+        if (pmask != 0u) {
+            const uint32_t nL = ~L;
+            const uint32_t pstart = rl(rec, HQ_REC_PSTART);
+            const HQ_CONST ProgTerm* pg = cro(P.prog) + pstart;
+            uint32_t um = pmask;
+            while (um) {
+                const int u = __builtin_ctz(um);
+                um &= um - 1u;
+                const uint32_t i0 = rl(pov, u), i1 = rl(pov, u + 1);
+                double c = 0.0;
+                for (uint32_t i = i0; i < i1; ++i) {
+                    const uint32_t mk = pg[i].mask;
+                    const double rt = pg[i].rate;
+                    c += (mk & nL) == 0u ? rt : 0.0;
+                }
+                double v;
+                if (u < B) {
+                    // low unit: its down-neighbour L \ u, read again (0 weight when u is idle)
+                    const bool bz = (L >> u) & 1u;
+                    c = bz ? c : 0.0;
+                    v = bload<T>(xr, bz ? (uint32_t)s_rank[L ^ (1u << u)] * SZ : 0u, o_dn);
+                } else {
+                    v = bload<T>(xr, t8, rl(rec, HQ_REC_HI + (u - B)) * SZ - base * SZ);
+                }
+                A = fma(MODE == S_PASS1 ? c : s.wa * c, v, A);
+            }
+        }
+        const double mu_m = mu_hi + mu_lo;
+        const double inv = recip(den_hi + mu_lo);
+        if (MODE == S_RESID) {
+            // in = p(n-1) U + p(n+1) D (weights), out = p(n) p_n(m) (Lambda + mu_m)
+            const double self_v = bload<T>(xr, t8, o_self) * s.is_self;
+            const double out = s.pself * self_v * (P.Lam + mu_m);
+            acc0 += fabs(A - out);
+            acc1 += out;
+        } else if (MODE == S_PASS1) {
+            const double Ut = A * s.wa * inv, Dt = Bs * s.wb * inv;
+            if (TRACK) {
+                acc0 = fma(mu_m, Ut, acc0);
+                acc1 = fma(mu_m, Dt, acc1);
+                acc2 = fmax(acc2, Ut);
+                const double v0 = s.alpha0 * Ut + s.beta0 * Dt;
+                acc3 = fmax(acc3, fabs(v0 - bload<T>(xr, t8, o_self) * s.is_self));
+            } else {
+                acc0 += Ut;
+                acc1 = fma(mu_m, Dt, acc1);
+            }
+        } else {
+            const T stored = (T)(A * inv);  // already scaled for storage
+            if (TRACK) acc2 = fmax(acc2, fabs((double)stored - bload<T>(xr, t8, o_self)) * s.is_self);
+            bstore<T>(xr, stored, t8, o_self);
+            const double ps = (double)stored * s.is_self;
+            acc0 += ps;
+            acc1 = fma(mu_m, ps, acc1);
+        }
+    }
+}
+
+template <typename T, int MODE, bool TRACK, int HF>
+__global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(5, 8))) void sweep_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
+                                                      int inner_one) {
+    __shared__ double s_w[WAVES * 64];
+    __shared__ uint16_t s_rank[1 << B];
+    __shared__ double s_red[4][WAVES];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int i = tid; i < (1 << B); i += HQ_WG) s_rank[i] = P.lo_rank[i];
+    __syncthreads();
+    const int n = A.n;
+    const Scal s = load_scal<MODE>(P, n, inner_one);
+    // the window of layers n - 1 .. n + 1 (offsets fit 32 bits up to N = 30)
+    const uint32_t base = cro(P.layer_off)[n - 1];
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(x + base, 0, -1, RSRC_W3);
+    const LowRow* rows = sizeof(T) == 8 ? P.lrow : P.lrow32;
+    const __amdgpu_buffer_rsrc_t rowr = __builtin_amdgcn_make_buffer_rsrc(const_cast<LowRow*>(rows), 0,
+                                                                          (1 << B) * (int)sizeof(LowRow), RSRC_W3);
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    // wave-granular segments; the eight XCDs sweep contiguous eighths
+    const uint32_t G = gridDim.x, wg = blockIdx.x;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    uint32_t begin, end, step;
+    if (G < 64 || (G & 7u)) {
+        begin = wg * WAVES + wv;
+        end = A.groups;
+        step = G * WAVES;
+    } else {
+        const uint32_t xcd = wg & 7u, per = (A.groups + 7u) >> 3;
+        const uint32_t lo = xcd * per;
+        begin = lo + (wg >> 3) * WAVES + wv;
+        end = min(A.groups, lo + per);
+        step = (G >> 3) * WAVES;
+    }
+    double* wlds = s_w + wv * 64;
+    // the record of segment i + 2 and the tile coefficients and program
+    // offsets of segment i + 1 are in flight while segment i is processed
+    const uint32_t* recs = P.srec + (size_t)A.desc_base * HQ_REC_WORDS;
+    auto load_rec = [&](uint32_t si) -> uint32_t {
+        return (si < end && lane < HQ_REC_WORDS) ? recs[(size_t)si * HQ_REC_WORDS + lane] : 0u;
+    };
+    auto load_tile = [&](uint32_t si, uint32_t rec, double& tcv, uint32_t& pov) {
+        tcv = 0.0;
+        pov = 0u;
+        if (si >= end) return;
+        const uint32_t Tb = rl(rec, HQ_REC_DESC) >> 4;
+        if (lane < P.N) tcv = P.tcoef[(size_t)Tb * P.N + lane];
+        if (rl(rec, HQ_REC_PMASK) != 0u && lane <= P.N)
+            pov = P.prog_off[(size_t)Tb * (P.N + 1) + lane] - rl(rec, HQ_REC_PSTART);
+    };
+    uint32_t rec0 = load_rec(begin), rec1 = load_rec(begin + step);
+    double tc0;
+    uint32_t pov0;
+    load_tile(begin, rec0, tc0, pov0);
+    for (uint32_t si = begin; si < end; si += step) {
+        const uint32_t rec2 = load_rec(si + 2 * step);
+        double tc1;
+        uint32_t pov1;
+        load_tile(si + step, rec1, tc1, pov1);
+        segment<T, MODE, TRACK, HF>(P, xr, rowr, base, rec0, tc0, pov0, s, wlds, s_rank, acc0, acc1, acc2, acc3);
+        rec0 = rec1;
+        rec1 = rec2;
+        tc0 = tc1;
+        pov0 = pov1;
+    }
+    // work-group partials (sum, sum, max, max); the finalize launch adds
+    // them in a fixed order
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    acc2 = wave_max(acc2);
+    acc3 = wave_max(acc3);
+    if (lane == 0) {
+        s_red[0][wv] = acc0;
+        s_red[1][wv] = acc1;
+        s_red[2][wv] = acc2;
+        s_red[3][wv] = acc3;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+        for (int i = 0; i < WAVES; ++i) {
+            b0 += s_red[0][i];
+            b1 += s_red[1][i];
+            b2 = fmax(b2, s_red[2][i]);
+            b3 = fmax(b3, s_red[3][i]);
+        }
+        double* pp = P.partials + (size_t)blockIdx.x * HQ_NPART;
+        pp[0] = b0;
+        pp[1] = b1;
+        pp[2] = b2;
+        pp[3] = b3;
+    }
+}
+
+}  // namespace hqsweep
+
+namespace hqk {
+
+using namespace hqsweep;
+
+static uint32_t sweep_grid(uint32_t groups) {
+    const uint32_t wgs = (groups + WAVES - 1) / WAVES;
+    if (wgs < 64) return wgs > 0 ? wgs : 1;
+    uint32_t g = wgs < HQ_GRID ? wgs : HQ_GRID;
+    return g & ~7u;
+}
+
+template <typename T, int HF>
+static void launch_h(int mode, bool track, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
+                     hipStream_t s) {
+    dim3 grid(sweep_grid(A.groups)), block(HQ_WG);
+    if (mode == 1 /* M_WRITE */ && !track)
+        hipLaunchKernelGGL((sweep_kernel<T, S_WRITE, false, HF>), grid, block, 0, s, P, A, x, inner_one);
+    else if (mode == 1)
+        hipLaunchKernelGGL((sweep_kernel<T, S_WRITE, true, HF>), grid, block, 0, s, P, A, x, inner_one);
+    else if (mode == 0 /* M_PASS1 */ && track)
+        hipLaunchKernelGGL((sweep_kernel<T, S_PASS1, true, HF>), grid, block, 0, s, P, A, x, inner_one);
+    else if (mode == 0)
+        hipLaunchKernelGGL((sweep_kernel<T, S_PASS1, false, HF>), grid, block, 0, s, P, A, x, inner_one);
+    else
+        hipLaunchKernelGGL((sweep_kernel<T, S_RESID, false, HF>), grid, block, 0, s, P, A, x, inner_one);
+}
+
+// Launch the sweep kernel of layer A.n for the default tile shape; returns
+// the number of work-groups (whose partials the finalize launch reads), or
+// 0 when this shape or layer is not covered (stored coefficients, another
+// tile width, the end layers of the residual).
+uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
+                      int inner_one, hipStream_t s) {
+    if (P.b != B || A.stored || !P.srec || !P.lrow || A.n < 1 || A.n >= P.N) return 0;
+#define HQ_SW(HV)                                                              \
+    case HV:                                                                   \
+        if (fp32)                                                              \
+            launch_h<float, HV>(mode, track, P, A, (float*)x, inner_one, s);   \
+        else                                                                   \
+            launch_h<double, HV>(mode, track, P, A, (double*)x, inner_one, s); \
+        break;
+    switch (P.H) {
+        HQ_SW(6) HQ_SW(7) HQ_SW(8) HQ_SW(9) HQ_SW(10) HQ_SW(11) HQ_SW(12) HQ_SW(13) HQ_SW(14) HQ_SW(15)
+        HQ_SW(16) HQ_SW(17) HQ_SW(18) HQ_SW(19) HQ_SW(20)
+        default:
+            return 0;
+    }
+#undef HQ_SW
+    return sweep_grid(A.groups);
+}
+
+}  // namespace hqk

@@ -55,7 +55,7 @@ INNER = {"closed": hq.HQ_INNER_CLOSED, "one": hq.HQ_INNER_ONE, "literal": hq.HQ_
 
 @pytest.mark.parametrize("inner", ["closed", "one", "literal"])
 @pytest.mark.parametrize("N,J,b,cfg", [(10, 40, 0, 1), (12, 60, 4, 2), (14, 120, 6, 3), (15, 90, 10, 2),
-                                       (13, 50, 12, 2), (16, 200, 8, 3)])
+                                       (13, 50, 12, 2), (16, 200, 8, 3), (16, 60, 0, 3), (17, 100, 0, 2)])
 def test_iteration_path_matches_oracle(N, J, b, cfg, inner):
     """Same iterate after k outer iterations (Gauss-Seidel across layers,
     the same inner reading), entry by entry, for several tile widths.  The
@@ -233,3 +233,50 @@ def test_literal_inner_loop_converges_to_the_same_law():
         assert np.abs(hq.hq_state(ctx) - ref.P).sum() <= 1e-10
     with pytest.raises(hq.HQError):
         hq.hq_solve_batch([_gpu(inst, inner=hq.HQ_INNER_LITERAL, delta=1e-6)], 1e-8)
+
+
+def test_fp64_residual_floor_ends_the_solve_early():
+    """A tolerance below what FP64 can reach: the residual stalls at its
+    rounding floor and the solve returns NOT_CONVERGED within a few hundred
+    iterations (not at max_iters = 100000), single and batched."""
+    inst = config_instance(1, 0)
+    say("case stall N=10 tol=1e-18")
+    ctx = _gpu(inst)
+    info = hq.hq_solve(ctx, 1e-18, allow_not_converged=True)
+    assert info["status"] == hq.HQ_ERR_NOT_CONVERGED
+    assert info["iterations"] < 2000 and info["residual"] < 1e-12
+    assert "stopped decreasing" in hq.hq_last_error()
+    ctxs = [_gpu(config_instance(1, i)) for i in range(3)]
+    st, infos = hq.hq_solve_batch(ctxs, 1e-18, allow_not_converged=True)
+    assert st == hq.HQ_ERR_NOT_CONVERGED
+    for x in infos:
+        assert x["status"] == hq.HQ_ERR_NOT_CONVERGED
+        assert x["iterations"] < 2000 and x["residual"] < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("inner", ["one", "closed", "literal"])
+def test_default_shape_sweep_matches_general_kernels(inner, prec, monkeypatch):
+    """The default-shape sweep kernels (10-bit tiles, from N = 16) against
+    the general layer kernels on the same instance: iterates after 1, 3 and
+    6 outer iterations and the balance residual agree to rounding."""
+    inst = config_instance(3, 7, N=18, J=300)
+    say(f"case sweep kernels vs general N=18 inner={inner} {prec}")
+    p = hq.HQ_FP32 if prec == "fp32" else hq.HQ_FP64
+    kw = dict(inner=INNER[inner], precision=p, delta=1e-6)
+    new = _gpu(inst, **kw)
+    monkeypatch.setenv("HQ_LEGACY_SWEEP", "1")
+    old = _gpu(inst, **kw)
+    monkeypatch.delenv("HQ_LEGACY_SWEEP")
+    done = 0
+    tol = 1e-12 if prec == "fp64" else 2e-7
+    for k in (1, 3, 6):
+        hq.hq_iterate(new, k - done)
+        hq.hq_iterate(old, k - done)
+        done = k
+        a, b = hq.hq_conditional(new), hq.hq_conditional(old)
+        assert _rel_close(a, b, tol) == 0, f"k={k}"
+        ra, rb = hq.hq_residual(new), hq.hq_residual(old)
+        assert ra == pytest.approx(rb, rel=1e-9 if prec == "fp64" else 1e-5)
+    hq.hq_destroy(new)
+    hq.hq_destroy(old)

@@ -21,8 +21,8 @@ def checker(tmp_path_factory):
     return exe
 
 
-def run(checker, tol, max_iters, fixed, r0, rate, floor):
-    r = subprocess.run([checker], input=f"{tol} {max_iters} {fixed} {r0} {rate} {floor}\n",
+def run(checker, tol, max_iters, fixed, r0, rate, floor, noise=0.0):
+    r = subprocess.run([checker], input=f"{tol} {max_iters} {fixed} {r0} {rate} {floor} {noise}\n",
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     what, k, checks = r.stdout.split()
@@ -47,6 +47,20 @@ def test_floor_above_tol_stalls_early(checker):
     what, k, checks = run(checker, 1e-18, 100000, 0, 1.0, 0.9, 1e-16)
     assert what == "stalled"
     assert k < 500 and checks < 40
+
+
+@pytest.mark.parametrize("noise", [0.3, 0.9])
+def test_noisy_floor_stalls_early(checker, noise):
+    # at the floor the residual fluctuates; fluctuations downwards must not
+    # keep the solve alive
+    what, k, checks = run(checker, 1e-18, 100000, 0, 1.0, 0.9, 1e-16, noise)
+    assert what == "stalled"
+    assert k < 1000 and checks < 80
+
+
+def test_noisy_decay_still_converges(checker):
+    what, k, _ = run(checker, 1e-8, 100000, 0, 1.0, 0.95, 0.0, 0.3)
+    assert what == "ok" and k <= 400
 
 
 def test_divergence_stalls_early(checker):
