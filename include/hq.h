@@ -240,6 +240,27 @@ hq_status hq_state(const hq_ctx* ctx, double* P);
  */
 hq_status hq_solve_batch(hq_ctx* const* ctxs, int count, double tol, hq_info* infos);
 
+/*
+ * hq_solve_batch for callers that cannot allocate device memory during the
+ * call: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as hq_solve_batch
+ * (the contexts are created beforehand and own their state vectors); the
+ * work queue, per-instance descriptors and results and the group-barrier
+ * counters and partials live in a static device array of about 0.8 MB that
+ * every GPU the library runs on holds until the process ends.  The call
+ * makes no device allocation: no hipMalloc or hipFree, no captured graph,
+ * no event; it runs on the first context's stream, uses the work-group
+ * size tuned by an earlier hq_solve_batch of the same batch signature (256
+ * otherwise), and returns after the batch has finished.
+ *   count  at most HQ_NOALLOC_MAX_BATCH (256); more is HQ_ERR_INVALID_ARG.
+ * Every call on one GPU shares that GPU's array and keeps the last call's
+ * contents in it (the counters are cleared by the launch itself).  Calls on
+ * one GPU must not overlap: the library serialises its own calls within a
+ * process, and each call finishes its device work before it returns.
+ */
+#define HQ_NOALLOC_MAX_BATCH 256
+hq_status hq_solve_batch_noalloc(hq_ctx* const* ctxs, int count, double tol, hq_info* infos);
+
 /* Release a context (NULL-safe). */
 void hq_destroy(hq_ctx* ctx);
 

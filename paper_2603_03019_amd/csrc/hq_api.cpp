@@ -44,6 +44,7 @@ hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, 
 hipError_t launch_batch(bool fp32, int block, const BatchItem* items, const BatchEntry* entries, BatchOut* outs,
                         int count, unsigned int* next, unsigned int* group_counts, int n_items, int grid,
                         hipStream_t s);
+hipError_t noalloc_scratch(int device, BatchScratch** out);
 }  // namespace hqk
 
 // automatic choice of stored-coefficient layers (see hq_create)
@@ -864,8 +865,14 @@ int device_cus() {
     return std::max(1, cus);
 }
 
+// One batched launch over contexts of one storage precision.  fixed ==
+// nullptr: the device's batch resources (allocated and grown on demand), a
+// work-group size autotuned per batch signature, and a captured graph.
+// fixed != nullptr: the static scratch of the allocation-free entry point,
+// no device allocation, no graph, no event; the work-group size is the
+// tuned one if this batch signature was tuned before, else 256.
 hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& pos, bool fp32, double tol,
-                      hq_info* infos, int device) {
+                      hq_info* infos, int device, BatchScratch* fixed) {
     const int count = (int)cs.size();
     std::vector<BatchItem> items(count);
     std::vector<int> order(count);
@@ -895,7 +902,31 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
         it.orig_bit = c->d_orig_bit;
     }
     std::lock_guard<std::mutex> lock(g_batch_mu);
-    BatchRes& r = batch_res(device, count);
+    BatchRes* r = nullptr;
+    BatchItem* d_items;
+    BatchEntry* d_entries;
+    BatchOut* d_outs;
+    unsigned int *d_next, *d_counts;
+    double* d_parts;
+    hipStream_t stream;
+    if (fixed) {
+        d_items = fixed->items;
+        d_entries = fixed->entries;
+        d_outs = fixed->outs;
+        d_next = fixed->next;
+        d_counts = fixed->group_counts;
+        d_parts = fixed->group_parts;
+        stream = cs[0]->stream;
+    } else {
+        r = &batch_res(device, count);
+        d_items = r->items;
+        d_entries = r->entries;
+        d_outs = r->outs;
+        d_next = r->next;
+        d_counts = r->group_counts;
+        d_parts = r->group_parts;
+        stream = r->stream;
+    }
     const int cus = device_cus();
     // Work sharing (hq_batchplan.h): an instance gets k work-groups, so that
     // the largest instances do not leave the rest of the device idle.
@@ -904,16 +935,18 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
         std::vector<double> sizes(count);
         for (int j = 0; j < count; ++j) {
             sizes[j] = std::ldexp(1.0, cs[order[j]]->N);
-            items[j].group_count = r.group_counts + j;
-            items[j].group_part = r.group_parts + (size_t)j * 2 * HQ_GROUP_MAX * 3;
+            items[j].group_count = d_counts + j;
+            items[j].group_part = d_parts + (size_t)j * 2 * HQ_GROUP_MAX * 3;
         }
         for (const hqplan::Entry& e : hqplan::plan(sizes, cus, HQ_GROUP_MAX))
             entries.push_back(BatchEntry{e.item, e.rank, e.k, 0});
     }
     const int n_entries = (int)entries.size();
+    if (fixed && n_entries > HQ_NOALLOC_MAX_BATCH * HQ_GROUP_MAX)
+        return fail(HQ_ERR_INVALID_ARG, "batch work plan exceeds the static scratch");
     const int grid = std::max(1, std::min(n_entries, 2 * cus));
-    HQ_HIP(hipMemcpyAsync(r.entries, entries.data(), sizeof(BatchEntry) * n_entries, hipMemcpyHostToDevice,
-                          r.stream));
+    HQ_HIP(hipMemcpyAsync(d_entries, entries.data(), sizeof(BatchEntry) * n_entries, hipMemcpyHostToDevice,
+                          stream));
     // autotuner: time each work-group size on this batch (a few iterations)
     std::string sig = std::string(fp32 ? "f32" : "f64") + ":" + std::to_string(count);
     {
@@ -926,22 +959,24 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
     auto tuned = g_batch_tuned.find(sig);
     if (tuned != g_batch_tuned.end()) {
         block = tuned->second;
+    } else if (fixed) {
+        block = 256;
     } else {
         std::vector<BatchItem> probe = items;
         for (auto& it : probe) {
             it.max_iters = std::min(it.max_iters, 6);
             it.check_every = 6;
         }
-        HQ_HIP(hipMemcpyAsync(r.items, probe.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, r.stream));
+        HQ_HIP(hipMemcpyAsync(d_items, probe.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, stream));
         hipEvent_t e0, e1;
         HQ_HIP(hipEventCreate(&e0));
         HQ_HIP(hipEventCreate(&e1));
         float best = 1e30f;
         for (int bs : {256, 512, 1024}) {
-            batch_launch(r, fp32, bs, n_entries, count, grid);  // warm-up (graph build)
-            HQ_HIP(hipEventRecord(e0, r.stream));
-            batch_launch(r, fp32, bs, n_entries, count, grid);
-            HQ_HIP(hipEventRecord(e1, r.stream));
+            batch_launch(*r, fp32, bs, n_entries, count, grid);  // warm-up (graph build)
+            HQ_HIP(hipEventRecord(e0, stream));
+            batch_launch(*r, fp32, bs, n_entries, count, grid);
+            HQ_HIP(hipEventRecord(e1, stream));
             HQ_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
             HQ_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -955,21 +990,29 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
         g_batch_tuned[sig] = block;
     }
     auto t0 = std::chrono::steady_clock::now();
-    HQ_HIP(hipMemcpyAsync(r.items, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, r.stream));
-    hipEvent_t k0, k1;
-    HQ_HIP(hipEventCreate(&k0));
-    HQ_HIP(hipEventCreate(&k1));
-    HQ_HIP(hipEventRecord(k0, r.stream));
-    batch_launch(r, fp32, block, n_entries, count, grid);
-    HQ_HIP(hipEventRecord(k1, r.stream));
+    HQ_HIP(hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, stream));
     std::vector<BatchOut> outs(count);
-    HQ_HIP(hipMemcpyAsync(outs.data(), r.outs, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, r.stream));
-    HQ_HIP(hipStreamSynchronize(r.stream));
     float kms = 0.f;
-    HQ_HIP(hipEventElapsedTime(&kms, k0, k1));
-    (void)hipEventDestroy(k0);
-    (void)hipEventDestroy(k1);
+    if (fixed) {
+        HQ_HIP(hqk::launch_batch(fp32, block, d_items, d_entries, d_outs, n_entries, d_next, d_counts, count, grid,
+                                 stream));
+        HQ_HIP(hipMemcpyAsync(outs.data(), d_outs, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, stream));
+        HQ_HIP(hipStreamSynchronize(stream));
+    } else {
+        hipEvent_t k0, k1;
+        HQ_HIP(hipEventCreate(&k0));
+        HQ_HIP(hipEventCreate(&k1));
+        HQ_HIP(hipEventRecord(k0, stream));
+        batch_launch(*r, fp32, block, n_entries, count, grid);
+        HQ_HIP(hipEventRecord(k1, stream));
+        HQ_HIP(hipMemcpyAsync(outs.data(), d_outs, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, stream));
+        HQ_HIP(hipStreamSynchronize(stream));
+        HQ_HIP(hipEventElapsedTime(&kms, k0, k1));
+        (void)hipEventDestroy(k0);
+        (void)hipEventDestroy(k1);
+    }
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (fixed) kms = (float)(wall * 1e3);  // no events in this form: the host clock around the launch
     hq_status worst = HQ_OK;
     for (int j = 0; j < count; ++j) {
         hq_ctx* c = cs[order[j]];
@@ -994,7 +1037,7 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
     return worst;
 }
 
-hq_status batch_impl(hq_ctx* const* ctxs, int count, double tol, hq_info* infos) {
+hq_status batch_impl(hq_ctx* const* ctxs, int count, double tol, hq_info* infos, bool noalloc) {
     if (count < 0 || (count > 0 && !ctxs)) return fail(HQ_ERR_INVALID_ARG, "bad batch arguments");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HQ_ERR_INVALID_ARG, "tol must be finite and > 0");
     std::vector<hq_ctx*> g64, g32;
@@ -1033,12 +1076,17 @@ hq_status batch_impl(hq_ctx* const* ctxs, int count, double tol, hq_info* infos)
         }
     }
     if (device >= 0) HQ_HIP(hipSetDevice(device));
+    BatchScratch* fixed = nullptr;
+    if (noalloc && device >= 0) {
+        // the per-device address of the static scratch (looked up once per device)
+        HQ_HIP(hqk::noalloc_scratch(device, &fixed));
+    }
     if (!g64.empty()) {
-        hq_status s = batch_group(g64, p64, false, tol, infos, device);
+        hq_status s = batch_group(g64, p64, false, tol, infos, device, fixed);
         if (s != HQ_OK && worst == HQ_OK) worst = s;
     }
     if (!g32.empty()) {
-        hq_status s = batch_group(g32, p32, true, tol, infos, device);
+        hq_status s = batch_group(g32, p32, true, tol, infos, device, fixed);
         if (s != HQ_OK && worst == HQ_OK) worst = s;
     }
     if (worst == HQ_ERR_NOT_CONVERGED) g_err = "some instances reached max_iters before tol";
@@ -1365,9 +1413,22 @@ int hq_num_units(const hq_ctx* ctx) { return ctx ? ctx->N : 0; }
 
 hq_status hq_solve_batch(hq_ctx* const* ctxs, int count, double tol, hq_info* infos) {
     try {
-        return batch_impl(ctxs, count, tol, infos);
+        return batch_impl(ctxs, count, tol, infos, false);
     } catch (const std::bad_alloc&) {
         return fail(HQ_ERR_OUT_OF_MEMORY, "allocation failed in hq_solve_batch");
+    } catch (const HipError& e) {
+        return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+    }
+}
+
+hq_status hq_solve_batch_noalloc(hq_ctx* const* ctxs, int count, double tol, hq_info* infos) {
+    if (count > HQ_NOALLOC_MAX_BATCH)
+        return fail(HQ_ERR_INVALID_ARG, "hq_solve_batch_noalloc takes at most " +
+                                            std::to_string(HQ_NOALLOC_MAX_BATCH) + " contexts");
+    try {
+        return batch_impl(ctxs, count, tol, infos, true);
+    } catch (const std::bad_alloc&) {
+        return fail(HQ_ERR_OUT_OF_MEMORY, "host allocation failed in hq_solve_batch_noalloc");
     } catch (const HipError& e) {
         return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
     }

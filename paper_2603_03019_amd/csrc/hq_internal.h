@@ -123,3 +123,19 @@ struct BatchOut {
     int iterations, checks, status, pad;
     double residual;
 };
+
+// Largest batch of the allocation-free batched solve, and the layout of its
+// scratch: the work queue, per-instance descriptors and results, the work
+// counter and the group barriers' counters and partial sums, all in one
+// static device array per GPU (hq_kernels.hip).
+#define HQ_NOALLOC_MAX_BATCH 256
+#define HQ_MAX_DEVICES 64  // device ordinals the per-device scratch addresses are kept for
+struct BatchScratch {
+    BatchItem items[HQ_NOALLOC_MAX_BATCH];
+    BatchEntry entries[HQ_NOALLOC_MAX_BATCH * HQ_GROUP_MAX];
+    BatchOut outs[HQ_NOALLOC_MAX_BATCH];
+    unsigned int group_counts[HQ_NOALLOC_MAX_BATCH];
+    unsigned int next[64];
+    double group_parts[HQ_NOALLOC_MAX_BATCH * 2 * HQ_GROUP_MAX * 3];
+};
+

@@ -31,6 +31,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace hq {
 
 #define HQ_ERR_DEVICE_CODE 3
@@ -1378,6 +1380,33 @@ hipError_t launch_batch(bool fp32, int block, const BatchItem* items, const Batc
     }
 #undef HQ_BATCH_CASE
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free batched solve: one copy of this array on
+// every GPU the library runs on, held until the process ends.  Host code
+// never passes `scratch` itself to a kernel (on the host it only names the
+// symbol); it uses the device address hipGetSymbolAddress returns for the
+// current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[sizeof(BatchScratch)];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[HQ_MAX_DEVICES] = {};
+
+hipError_t noalloc_scratch(int device, BatchScratch** out) {
+    *out = nullptr;
+    if (device < 0 || device >= HQ_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = static_cast<BatchScratch*>(g_scratch_ptr[device]);
+    return hipSuccess;
 }
 
 hipError_t launch_dispatch(double* G, int N, int J, const int32_t* pref, double* q, const double* lam,
