@@ -41,6 +41,8 @@ hipError_t launch_dispatch(double* G, int N, int J, const int32_t* pref, double*
 hipError_t launch_widen(const float* src, double* dst, uint32_t begin, uint32_t count, double factor,
                         hipStream_t s);
 hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, uint32_t nnodes, hipStream_t s);
+hipError_t launch_lookahead(const SweepParams& P, const LayerArgs& A, double* w, double* z, uint32_t nnodes,
+                            hipStream_t s);
 hipError_t launch_batch(bool fp32, int block, const BatchItem* items, const BatchEntry* entries, BatchOut* outs,
                         int count, unsigned int* next, unsigned int* group_counts, int n_items, int grid,
                         hipStream_t s);
@@ -140,10 +142,13 @@ struct hq_ctx {
     uint16_t *d_lo_unrank = nullptr, *d_lo_rank = nullptr;
     TrieNode* d_nodes = nullptr;
     unsigned int* d_counters = nullptr;
+    double* d_la = nullptr;      // look-ahead closed form: w(l), then z(l), per state (2 * 2^N)
     uint32_t* d_srec = nullptr;  // segment records of the default-shape sweep
     LowRow* d_lrow = nullptr;    // its low-pattern rows (FP64 offsets)
     LowRow* d_lrow32 = nullptr;  // and with FP32 offsets
     SweepParams P64{}, P32{};
+    bool use_graphs = true;            // replay captured iterations (HQ_NO_GRAPH=1: launch eagerly)
+    hipGraphExec_t iter_exec[2][2] = {};  // [FP32 storage][delta tracking]
     bool have_iterate = false;
     bool learned = false;      // product-form weights came from the network
     bool active_fp32 = false;  // storage of the current iterate
@@ -155,12 +160,17 @@ struct hq_ctx {
                         d_scale64, d_scale32,  d_rho,      d_xu,       d_given,     d_binom,    d_layer_off,
                         d_lo_qstart, d_prog_off, d_prog, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
                         d_counters, d_seg_desc, d_segoff,   d_coefs,     d_seg_prog, d_G,
-                        d_q,       d_lam_in,   d_travel,   d_tsum,     d_pref_in,  d_srec,      d_lrow,
+                        d_q,       d_lam_in,   d_travel,   d_tsum,     d_pref_in,  d_srec,      d_lrow,     d_la,
                         d_lrow32};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         x64 = nullptr;
         x32 = nullptr;
+        for (auto& row : iter_exec)
+            for (auto& e : row) {
+                if (e) (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         ev0 = ev1 = nullptr;
@@ -276,6 +286,10 @@ void setup_params(hq_ctx* c) {
     P.sc.rden = c->d_scal + 5 * L;
     P.sc.delta = c->d_scal + 6 * L;
     P.sc.misc = c->d_scal + 7 * L;
+    P.sc.wsum = c->d_scal + 8 * L + 8;
+    P.sc.zsum = c->d_scal + 9 * L + 8;
+    P.la_w = c->d_la;
+    P.la_z = c->d_la ? c->d_la + c->states() : nullptr;
     P.srec = c->d_srec;
     P.lrow = c->d_lrow;
     P.lrow32 = c->d_lrow32;
@@ -407,6 +421,9 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     std::vector<uint32_t> srec;
     std::vector<LowRow> lrow, lrow32;
     const char* legacy = std::getenv("HQ_LEGACY_SWEEP");
+    const char* nograph = std::getenv("HQ_NO_GRAPH");
+    const char* nola = std::getenv("HQ_NO_LOOKAHEAD");
+    c->use_graphs = !(nograph && nograph[0] == '1');
     if (b == HQ_SWEEP_B && c->H >= 6 && c->H <= 20 && !(legacy && legacy[0] == '1')) {
         lrow = hqsweeptab::low_rows(lay, c->nu, 8);
         lrow32 = hqsweeptab::low_rows(lay, c->nu, 4);
@@ -498,7 +515,7 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->d_nu = dalloc<double>(N);
         c->d_mu_lo = dalloc<double>(lo);
         c->d_tcoef = dalloc<double>(tcoef.size());
-        c->d_scal = dalloc<double>(8 * (N + 1) + 8);
+        c->d_scal = dalloc<double>(10 * (N + 1) + 8);
         c->d_part = dalloc<double>(max_groups * 32);
         c->d_scale64 = dalloc<double>(s64.size());
         c->d_scale32 = dalloc<double>(s32.size());
@@ -518,6 +535,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->d_lo_rank = dalloc<uint16_t>(lo_rank.size());
         c->d_nodes = dalloc<TrieNode>(c->nodes.size());
         c->d_counters = dalloc<unsigned int>(N + 1);
+        // the look-ahead closed form (one pass per layer) needs the default-shape
+        // sweep, which accumulates its sums while it writes
+        if (o.inner == HQ_INNER_CLOSED && !srec.empty() && !(nola && nola[0] == '1'))
+            c->d_la = dalloc<double>(2 * S);
         if (!srec.empty()) {
             c->d_srec = dalloc<uint32_t>(srec.size());
             c->d_lrow = dalloc<LowRow>(lrow.size());
@@ -547,12 +568,16 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
             h2d(c->d_lrow32, lrow32, s);
         }
         HQ_HIP(hipMemsetAsync(c->d_counters, 0, sizeof(unsigned int) * (N + 1), s));
-        HQ_HIP(hipMemsetAsync(c->d_scal, 0, sizeof(double) * (8 * (N + 1) + 8), s));
+        HQ_HIP(hipMemsetAsync(c->d_scal, 0, sizeof(double) * (10 * (N + 1) + 8), s));
         if (!c->state_init.empty()) {
             c->d_given = dalloc<double>(S);
             HQ_HIP(hipMemcpyAsync(c->d_given, c->state_init.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
         }
         setup_params(c.get());
+        if (c->d_la)
+            for (int n = 0; n <= N; ++n)
+                HQ_HIP(hqk::launch_lookahead(c->P64, c->layers[n], c->d_la, c->d_la + S, (uint32_t)c->nodes.size(),
+                                             s));
         for (int n = 1; n <= N - 1; ++n)
             if (c->layers[n].stored)
                 HQ_HIP(hqk::launch_coef(c->P64, c->layers[n], c->d_coefs, (uint32_t)c->nodes.size(), s));
@@ -601,15 +626,49 @@ void run_init(hq_ctx* c, bool fp32) {
     c->iterations_done = 0;
 }
 
-void run_sweep(hq_ctx* c, bool track_delta) {
+// The launches of one outer iteration: for n = 1..N-1 in order, the layer
+// kernel (and for the closed and literal inner forms its first pass) with
+// the finalize launch that forms the layer's scalars.
+void launch_iteration(hq_ctx* c, bool track_delta) {
     const bool fp32 = c->active_fp32;
     const int inner = c->opts.inner;  // 0 closed, 1 one update, 2 literal loop
     for (int n = 1; n <= c->N - 1; ++n) {
         const LayerArgs& A = c->layers[n];
-        if (inner != HQ_INNER_ONE)
+        // the closed form's first pass is not needed when its sums come from
+        // the look-ahead (alpha_n is then already on the device)
+        if (inner == HQ_INNER_LITERAL || (inner == HQ_INNER_CLOSED && !c->d_la))
             HQ_HIP(hqk::launch_layer(M_PASS1, inner == HQ_INNER_LITERAL, fp32, c->params(fp32), A, c->xbuf(fp32),
                                      inner, c->stream));
         HQ_HIP(hqk::launch_layer(M_WRITE, track_delta, fp32, c->params(fp32), A, c->xbuf(fp32), inner, c->stream));
+    }
+}
+
+// One outer iteration.  Its 2(N-1) (or 4(N-1)) launches depend only on
+// device memory, so they are captured once per storage precision and
+// stopping rule as a graph of kernel nodes and replayed.
+void run_sweep(hq_ctx* c, bool track_delta) {
+    if (c->use_graphs) {
+        hipGraphExec_t& ex = c->iter_exec[c->active_fp32 ? 1 : 0][track_delta ? 1 : 0];
+        if (!ex) {
+            hipGraph_t g = nullptr;
+            HQ_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t le = hipSuccess;
+            try {
+                launch_iteration(c, track_delta);
+            } catch (const HipError& e) {
+                le = e.e;
+            }
+            const hipError_t ce = hipStreamEndCapture(c->stream, &g);
+            HQ_HIP(le);
+            HQ_HIP(ce);
+            const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) ex = nullptr;
+            HQ_HIP(ie);
+        }
+        HQ_HIP(hipGraphLaunch(ex, c->stream));
+    } else {
+        launch_iteration(c, track_delta);
     }
     c->iterations_done++;
 }

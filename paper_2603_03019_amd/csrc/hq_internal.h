@@ -11,7 +11,7 @@
 #define HQ_MAXB 12          // largest low-bit tile width b
 #define HQ_MAXH 26          // largest high-bit count H = N - b
 #define HQ_WG 256           // threads per work-group of the layer kernels
-#define HQ_NPART 4          // partials per work-group of the layer kernels (sum, sum, max, max)
+#define HQ_NPART 6          // partials per work-group of the layer kernels (sum, sum, max, max, sum, sum)
 #ifndef HQ_HCHUNK
 #define HQ_HCHUNK 8         // high-unit neighbour loads issued together by the run-time-shape sweep
 #endif
@@ -44,6 +44,8 @@ struct DevScalars {
     double* rden;
     double* delta;
     double* misc;  // [0] residual, [1] total mass, [2] error flag (non-finite seen)
+    double* wsum;  // look-ahead closed form: sum_{C_n} p_n(l) w(l) of the last write of layer n
+    double* zsum;  //   and sum_{C_n} p_n(l) z(l)
 };
 
 // Everything a layer kernel needs about the instance and the layout.
@@ -68,6 +70,8 @@ struct SweepParams {
     const uint2* seg_prog;       // per seg_desc entry: (first program term, term count) of its tile
     const TrieNode* nodes;
     const double* coefs;         // stored coefficients of the top layers (unit-major per layer)
+    const double* la_w;          // look-ahead closed form: w(l) per state (layout order), or null
+    const double* la_z;          //   and z(l)
     const double* scale;         // [N+1] storage scale of each layer (x = scale * p)
     const double* inv_scale;     // [N+1]
     DevScalars sc;

@@ -88,74 +88,78 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Reduce four per-thread values over the work-group (sum, sum, max, max)
-// and store them as this work-group's partial.  No fence: the finalize
-// kernel that reads the partials runs after this kernel on the same stream.
-__device__ void block_partial(double a0, double a1, double a2, double a3, double* partials) {
-    __shared__ double s_red[4][HQ_WG / 64];
+// Reduce six per-thread values over the work-group (sum, sum, max, max,
+// sum, sum) and store them as this work-group's partial.  No fence: the
+// finalize kernel that reads the partials runs after this kernel on the
+// same stream.
+__device__ void block_partial(double a0, double a1, double a2, double a3, double* partials, double a4 = 0.0,
+                              double a5 = 0.0) {
+    __shared__ double s_red[HQ_NPART][HQ_WG / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
     a2 = wave_max(a2);
     a3 = wave_max(a3);
+    a4 = wave_sum(a4);
+    a5 = wave_sum(a5);
     if (lane == 0) {
         s_red[0][w] = a0;
         s_red[1][w] = a1;
         s_red[2][w] = a2;
         s_red[3][w] = a3;
+        s_red[4][w] = a4;
+        s_red[5][w] = a5;
     }
     __syncthreads();
     if (tid == 0) {
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+        double b[HQ_NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int i = 0; i < HQ_WG / 64; ++i) {
-            b0 += s_red[0][i];
-            b1 += s_red[1][i];
-            b2 = fmax(b2, s_red[2][i]);
-            b3 = fmax(b3, s_red[3][i]);
+            b[0] += s_red[0][i];
+            b[1] += s_red[1][i];
+            b[2] = fmax(b[2], s_red[2][i]);
+            b[3] = fmax(b[3], s_red[3][i]);
+            b[4] += s_red[4][i];
+            b[5] += s_red[5][i];
         }
         double* pp = partials + (size_t)blockIdx.x * HQ_NPART;
-        pp[0] = b0;
-        pp[1] = b1;
-        pp[2] = b2;
-        pp[3] = b3;
+        for (int j = 0; j < HQ_NPART; ++j) pp[j] = b[j];
     }
 }
 
 // Fixed-order reduction of `count` partials by one work-group.
-__device__ void sum_partials(const double* partials, uint32_t count, double out[4]) {
-    __shared__ double s_red[4][HQ_WG / 64];
+__device__ void sum_partials(const double* partials, uint32_t count, double out[HQ_NPART]) {
+    __shared__ double s_red[HQ_NPART][HQ_WG / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    double c[HQ_NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (uint32_t i = tid; i < count; i += HQ_WG) {
         const double* pp = partials + (size_t)i * HQ_NPART;
-        c0 += pp[0];
-        c1 += pp[1];
-        c2 = fmax(c2, pp[2]);
-        c3 = fmax(c3, pp[3]);
+        c[0] += pp[0];
+        c[1] += pp[1];
+        c[2] = fmax(c[2], pp[2]);
+        c[3] = fmax(c[3], pp[3]);
+        c[4] += pp[4];
+        c[5] += pp[5];
     }
-    c0 = wave_sum(c0);
-    c1 = wave_sum(c1);
-    c2 = wave_max(c2);
-    c3 = wave_max(c3);
-    if (lane == 0) {
-        s_red[0][w] = c0;
-        s_red[1][w] = c1;
-        s_red[2][w] = c2;
-        s_red[3][w] = c3;
-    }
+    c[0] = wave_sum(c[0]);
+    c[1] = wave_sum(c[1]);
+    c[2] = wave_max(c[2]);
+    c[3] = wave_max(c[3]);
+    c[4] = wave_sum(c[4]);
+    c[5] = wave_sum(c[5]);
+    if (lane == 0)
+        for (int j = 0; j < HQ_NPART; ++j) s_red[j][w] = c[j];
     __syncthreads();
     if (tid == 0) {
-        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        double d[HQ_NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int i = 0; i < HQ_WG / 64; ++i) {
-            d0 += s_red[0][i];
-            d1 += s_red[1][i];
-            d2 = fmax(d2, s_red[2][i]);
-            d3 = fmax(d3, s_red[3][i]);
+            d[0] += s_red[0][i];
+            d[1] += s_red[1][i];
+            d[2] = fmax(d[2], s_red[2][i]);
+            d[3] = fmax(d[3], s_red[3][i]);
+            d[4] += s_red[4][i];
+            d[5] += s_red[5][i];
         }
-        out[0] = d0;
-        out[1] = d1;
-        out[2] = d2;
-        out[3] = d3;
+        for (int j = 0; j < HQ_NPART; ++j) out[j] = d[j];
     }
 }
 
@@ -347,7 +351,7 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
                                                 const SegScal& sc, const SegVec& r, const uint16_t* s_rank,
                                                 const uint16_t* s_unrank, const uint32_t* s_qstart,
                                                 const ModeScalars& ms, double& acc0, double& acc1, double& acc2,
-                                                double& acc3) {
+                                                double& acc3, double& acc4, double& acc5) {
     constexpr int MAXB = BF ? BF : HQ_MAXB, MAXH = HF ? HF : HQ_MAXH;
     const int lane = threadIdx.x & 63;
     const int n = A.n, N = P.N;
@@ -483,6 +487,10 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
                 const double ps = (double)stored * is_self;
                 acc0 += ps;
                 acc1 += mu_m * ps;
+                if (P.la_w) {
+                    acc4 += ps * P.la_w[o];
+                    acc5 += ps * P.la_z[o];
+                }
             }
         }
     }
@@ -496,9 +504,9 @@ __device__ __forceinline__ void segment_update(const SweepParams& P, const Layer
                                                double& acc1, double& acc2) {
     const SegScal sc = fetch_scal(P, A, si);
     const SegVec r = fetch_vec(P, P.b, P.H, sc, STORED);
-    double unused = 0.0;
+    double unused = 0.0, unused4 = 0.0, unused5 = 0.0;
     segment_compute<T, MODE, TRACK_DELTA, STORED>(P, A, x, sc, r, s_rank, s_unrank, s_qstart, ms, acc0, acc1, acc2,
-                                                  unused);
+                                                  unused, unused4, unused5);
 }
 
 template <typename T, int MODE, bool TRACK_DELTA, bool STORED, int BF = 0, int HF = 0>
@@ -517,7 +525,7 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
     if (tid <= b + 1) s_qstart[tid] = P.lo_qstart[tid];
     __syncthreads();
     const ModeScalars ms = mode_scalars<MODE>(P, A.n, inner_one, P.sc.lam, P.sc.mu, P.sc.alpha, P.sc.pn);
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0, acc5 = 0.0;
     // Software pipeline over this wave's segments: the scalar record of
     // segment i+2 and the lane-parallel record of segment i+1 are in flight
     // while segment i is processed.
@@ -535,20 +543,36 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
         if (si + it.step < it.end) v1 = fetch_vec(P, b, H, s1, STORED);
         if (si + 2 * it.step < it.end) s2 = fetch_scal(P, A, si + 2 * it.step);
         segment_compute<T, MODE, TRACK_DELTA, STORED, BF, HF>(P, A, x, s0, v0, s_rank, s_unrank, s_qstart, ms, acc0,
-                                                              acc1, acc2, acc3);
+                                                              acc1, acc2, acc3, acc4, acc5);
         s0 = s1;
         v0 = v1;
         s1 = s2;
     }
-    block_partial(acc0, acc1, acc2, acc3, P.partials);
+    block_partial(acc0, acc1, acc2, acc3, P.partials, acc4, acc5);
 }
 
 // Layer scalars from the work-group partials of the kernel just run on the
 // same stream (one work-group, fixed summation order).
 // inner: 0 closed form, 1 one update, 2 literal loop with tolerance P.delta.
+// With the look-ahead closed form (P.la_w set): the write of layer n also
+// yields sum p_n w and sum p_n z, from which the closed-form alpha of layer
+// n + 1 follows before that layer is swept:
+//   alpha_{n+1} = beta_{n+1} S_muD(n+1) / (Lambda S_U(n+1)),
+//   S_U(n+1) = sum_{C_n} p_n w (this iteration), S_muD(n+1) = sum_{C_{n+2}}
+//   p_{n+2} z (the last write of layer n + 2, i.e. the previous iteration),
+// the same sums the first pass forms, re-indexed over the neighbour layers.
+__device__ __forceinline__ void lookahead_alpha(const SweepParams& P, int m) {
+    // alpha of layer m from the stored sums; m in 1..N-1
+    const double beta = P.sc.lam[m] / P.sc.mu[m + 1];
+    const double su = P.sc.wsum[m - 1], smud = P.sc.zsum[m + 1];
+    const double a = beta * smud / (P.Lam * su);
+    if (!(su > 0.0) || !isfinite(a)) P.sc.misc[2] = 1.0;
+    P.sc.alpha[m] = a;
+}
+
 __global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode, int n, uint32_t count,
                                                          int inner_one) {
-    double tot[4];
+    double tot[HQ_NPART];
     sum_partials(P.partials, count, tot);
     if (threadIdx.x != 0) return;
     double* misc = P.sc.misc;
@@ -586,6 +610,12 @@ __global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode
         P.sc.mu[n] = mu;
         P.sc.alpha[n] = used;
         P.sc.delta[n] = tot[2];
+        if (P.la_w) {
+            P.sc.wsum[n] = tot[4];
+            P.sc.zsum[n] = tot[5];
+            // the next layer of this iteration, or layer 1 of the next one
+            lookahead_alpha(P, n + 1 <= N - 1 ? n + 1 : 1);
+        }
     } else if (mode == M_RESID) {
         P.sc.rnum[n] = tot[0];
         P.sc.rden[n] = tot[1];
@@ -595,6 +625,11 @@ __global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode
         P.sc.mu[n] = tot[1];
         P.sc.alpha[n] = 0.0;
         P.sc.delta[n] = 0.0;
+        if (P.la_w) {
+            P.sc.wsum[n] = tot[4];
+            P.sc.zsum[n] = tot[5];
+            if (n == N && N >= 2) lookahead_alpha(P, 1);  // every layer's sums are in
+        }
     }
 }
 
@@ -631,6 +666,50 @@ __global__ __launch_bounds__(HQ_WG) void coef_kernel(SweepParams P, LayerArgs A,
     }
 }
 
+// Per-state constants of the look-ahead closed form, for every state l of
+// one layer, at its position in the state vector:
+//   w(l) = sum_{u notin l} r(l, u) / (Lambda + mu_l + nu_u),
+//   z(l) = sum_{u in l} nu_u (mu_l - nu_u) / (Lambda + mu_l - nu_u),
+// with r(l, u) the arrival rate that l sends to its idle unit u (the demand
+// nodes whose first idle unit in l is u, eq. (3)).  r comes from the merged
+// preference trie: a node on a busy path whose own unit is idle passes its
+// whole rate to that unit.
+__global__ __launch_bounds__(HQ_WG) void lookahead_kernel(SweepParams P, LayerArgs A, double* __restrict__ w,
+                                                          double* __restrict__ z, uint32_t nnodes) {
+    const int tid = threadIdx.x;
+    const int n = A.n, b = P.b, N = P.N;
+    const uint32_t tiles = 1u << P.H;
+    const SegIter it = seg_iter(A.groups);
+    for (uint32_t si = it.begin; si < it.end; si += it.step) {
+        const Seg sg = seg_at(P, A, si);
+        const uint32_t off = P.segoff[sg.q * tiles + sg.Tb];
+        const uint32_t cnt = C(P.binom, b, sg.q);
+        for (uint32_t t = tid; t < cnt; t += HQ_WG) {
+            const uint32_t m = (sg.Tb << b) | P.lo_unrank[P.lo_qstart[sg.q] + t];
+            double mu_m = 0.0;
+            for (int u = 0; u < N; ++u)
+                if ((m >> u) & 1u) mu_m += P.nu[u];
+            double wv = 0.0, zv = 0.0;
+            uint32_t i = 0;
+            while (i < nnodes) {
+                const TrieNode nd = P.nodes[i];
+                if ((m & nd.need) == nd.need) {
+                    ++i;  // unit busy: the calls go on down the list
+                } else {
+                    const int u = (int)(nd.skip_unit & 31u);  // first idle unit of these calls
+                    wv += nd.rate / (P.Lam + mu_m + P.nu[u]);
+                    i = nd.skip_unit >> 5;
+                }
+            }
+            for (int u = 0; u < N; ++u)
+                if ((m >> u) & 1u) zv += P.nu[u] * (mu_m - P.nu[u]) / (P.Lam + mu_m - P.nu[u]);
+            w[off + t] = wv;
+            z[off + t] = zv;
+        }
+    }
+    (void)n;
+}
+
 // Initial iterate of one layer: uniform 1/C(N,n) (Algorithm 1 step 2),
 // product form prod_{u in m} x_u / e_n(x), or a given state (bitmask order,
 // original unit labels mapped through `orig_bit`).  Partials for lambda(n), mu(n).
@@ -641,7 +720,8 @@ template <typename T>
 __device__ __forceinline__ void init_segment(const SweepParams& P, const LayerArgs& A, T* __restrict__ x,
                                              uint32_t si, int init_mode, const double* __restrict__ xu,
                                              const double* __restrict__ given,
-                                             const uint32_t* __restrict__ orig_bit, double& acc0, double& acc1) {
+                                             const uint32_t* __restrict__ orig_bit, double& acc0, double& acc1,
+                                             double& acc4, double& acc5) {
     const int lane = threadIdx.x & 63;
     const int n = A.n, b = P.b, H = P.H, N = P.N;
     const uint32_t tiles = 1u << H;
@@ -683,6 +763,10 @@ __device__ __forceinline__ void init_segment(const SweepParams& P, const LayerAr
             if ((L >> l) & 1u) mu_lo += ro(P.nu)[l];
         acc0 += ps;
         acc1 += (mu_hi + mu_lo) * ps;
+        if (P.la_w) {
+            acc4 += ps * P.la_w[off + t];
+            acc5 += ps * P.la_z[off + t];
+        }
     }
 }
 
@@ -695,11 +779,11 @@ __global__ __launch_bounds__(HQ_WG) void init_kernel(SweepParams P, LayerArgs A,
                                                      const double* __restrict__ xu,
                                                      const double* __restrict__ given,
                                                      const uint32_t* __restrict__ orig_bit) {
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc0 = 0.0, acc1 = 0.0, acc4 = 0.0, acc5 = 0.0;
     const WaveIter it = wave_iter(A.groups);
     for (uint32_t si = it.begin; si < it.end; si += it.step)
-        init_segment<T>(P, A, x, si, A.init_mode, xu, given, orig_bit, acc0, acc1);
-    block_partial(acc0, acc1, 0.0, 0.0, P.partials);
+        init_segment<T>(P, A, x, si, A.init_mode, xu, given, orig_bit, acc0, acc1, acc4, acc5);
+    block_partial(acc0, acc1, 0.0, 0.0, P.partials, acc4, acc5);
 }
 
 // Birth-death marginal p(n), n = 0..N, of (10) from lambda(n), mu(n), with
@@ -1015,9 +1099,9 @@ __global__ __launch_bounds__(BS) void batch_kernel(const BatchItem* __restrict__
         __syncthreads();
         // initial iterate and its layer scalars (13)-(14)
         for (int n = 0; n <= N; ++n) {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, la4 = 0.0, la5 = 0.0;  // (look-ahead sums unused here)
             for (uint32_t si = first; si < B.layers[n].groups; si += stride)
-                init_segment<T>(P, B.layers[n], x, si, B.init_mode, B.xu, B.given, B.orig_bit, a0, a1);
+                init_segment<T>(P, B.layers[n], x, si, B.init_mode, B.xu, B.given, B.orig_bit, a0, a1, la4, la5);
             group_sum3<BS>(a0, a1, a2, s_red, g, &s_flag);
             if (tid == 0) {
                 s_lam[n] = (n == N) ? 0.0 : P.Lam * a0;
@@ -1310,6 +1394,12 @@ hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams
             launch_layer_s<double, false>(mode, track_delta, P, A, (double*)x, inner_one, s);
     }
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(HQ_WG), 0, s, P, mode, A.n, grid_for(A.groups), inner_one);
+    return hipGetLastError();
+}
+
+hipError_t launch_lookahead(const SweepParams& P, const LayerArgs& A, double* w, double* z, uint32_t nnodes,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(lookahead_kernel, dim3(grid_for(A.groups)), dim3(HQ_WG), 0, s, P, A, w, z, nnodes);
     return hipGetLastError();
 }
 

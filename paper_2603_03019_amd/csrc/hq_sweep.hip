@@ -131,22 +131,44 @@ __device__ __forceinline__ Scal load_scal(const SweepParams& P, int n, int inner
     return s;
 }
 
+// Sum of the rates of unit u's program terms whose low mask lies in L (the
+// terms of the segment's tile: the first 64 held lane-parallel, mask in tmk
+// and rate in trt, the rest read as scalar loads).
+__device__ __forceinline__ double unit_terms(const HQ_CONST ProgTerm* pg, uint32_t pov, uint32_t tmk, double trt,
+                                             int u, uint32_t nL) {
+    const uint32_t i0 = rl(pov, u), i1 = rl(pov, u + 1);
+    double c = 0.0;
+    for (uint32_t i = i0; i < i1; ++i) {
+        uint32_t mk;
+        double rt;
+        if (i < 64) {
+            mk = rl(tmk, (int)i);
+            rt = rld(trt, (int)i);
+        } else {
+            mk = pg[i].mask;
+            rt = pg[i].rate;
+        }
+        c += (mk & nL) == 0u ? rt : 0.0;
+    }
+    return c;
+}
+
 // One wave, one segment.  HF = H (high bits), fixed at compile time.
 template <typename T, int MODE, bool TRACK, int HF>
 __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rsrc_t xr,
                                         __amdgpu_buffer_rsrc_t rowr, const uint32_t base, const uint32_t rec,
-                                        const double tcv, const uint32_t pov, const Scal& s, double* wlds,
-                                        const uint16_t* s_rank, double& acc0, double& acc1, double& acc2,
-                                        double& acc3) {
+                                        const double tcv, const uint32_t pov, const uint32_t tmk, const double trt,
+                                        const Scal& s, double* wlds, T* stage, const uint16_t* s_rank,
+                                        double& acc0, double& acc1, double& acc2, double& acc3, double& acc4,
+                                        double& acc5, const double* la_w, const double* la_z) {
     constexpr uint32_t SZ = sizeof(T);
     const int lane = threadIdx.x & 63;
     const uint32_t desc = rl(rec, HQ_REC_DESC);
     const int q = (int)(desc & 15u);
     const uint32_t Tb = desc >> 4;
-    // scalar byte offsets inside the window (layers n-1 .. n+1)
+    // scalar byte offsets inside the window (layers n-1 .. n+1); a segment
+    // without down- or up-neighbour segment gets 0, which nothing then reads
     const uint32_t o_self = (rl(rec, HQ_REC_SELF) - base) * SZ;
-    // (a segment without down- or up-neighbour segment gets offset 0, the
-    // window's first element, which no lane then reads)
     const uint32_t o_dn = q > 0 ? (rl(rec, HQ_REC_DN) - base) * SZ : 0u;
     const uint32_t o_up = q < B ? (rl(rec, HQ_REC_UP) - base) * SZ : 0u;
     uint32_t o_hi[HF];
@@ -156,22 +178,23 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
         (long long)(((unsigned long long)rl(rec, HQ_REC_MUHI + 1) << 32) | rl(rec, HQ_REC_MUHI)));
     const double den_hi = P.Lam + mu_hi;
     const uint32_t cnt = cro(P.binom)[B * 32 + q];
+    const uint32_t cnt_dn = q > 0 ? cro(P.binom)[B * 32 + q - 1] : 0u;
+    const uint32_t cnt_up = q < B ? cro(P.binom)[B * 32 + q + 1] : 0u;
     const uint32_t qs = cro(P.lo_qstart)[q];
     const uint32_t pmask = rl(rec, HQ_REC_PMASK);
+    const HQ_CONST ProgTerm* pg = cro(P.prog) + rl(rec, HQ_REC_PSTART);
     // weights: lane u < N holds unit u's; alpha-side for busy units (tile
     // coefficient), beta-side for idle ones (service rate)
     const double nu_l = lane < P.N ? cro(P.nu)[lane] : 0.0;
     const bool busy_hi = lane >= B && lane < P.N && ((Tb >> (lane - B)) & 1u);
-    double wA = 0.0, wB = 0.0;  // PASS1 keeps the two sides apart (side factors applied at the end)
-    if (MODE == S_PASS1) {
-        wA = busy_hi ? tcv : 0.0;
-        wB = busy_hi ? 0.0 : nu_l;
-    } else {
-        wA = busy_hi ? s.wa * tcv : s.wb * nu_l;
-    }
-    // the weights into this wave's LDS slots: low unit l busy at [l], idle
-    // at [16 + l]; high unit B + k at [32 + k] (PASS1: busy side there and
-    // idle side at [48 + k]; the side factors are applied at the end)
+    // (PASS1 keeps the two sides apart, side factors applied at the end)
+    const double wA = MODE == S_PASS1 ? (busy_hi ? tcv : nu_l) : (busy_hi ? s.wa * tcv : s.wb * nu_l);
+    // The previous segment's LDS reads of this wave are done (a wave's LDS
+    // operations complete in order).  Then the weights go to this wave's
+    // slots: low unit l busy at [l], idle at [16 + l]; high unit B + k at
+    // [32 + k]; and the
+    // low-neighbour segments (T, q - 1) of layer n - 1 and (T, q + 1) of
+    // layer n + 1 go to this wave's staging area, one after the other.
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (lane < B) {
@@ -179,8 +202,9 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
         wlds[16 + lane] = MODE == S_PASS1 ? nu_l : s.wb * nu_l;
     } else if (lane < P.N) {
         wlds[32 + lane - B] = wA;
-        if (MODE == S_PASS1) wlds[48 + lane - B] = wB;
     }
+    for (uint32_t i = lane; i < cnt_dn; i += 64) stage[i] = (T)bload<T>(xr, i * SZ, o_dn);
+    for (uint32_t i = lane; i < cnt_up; i += 64) stage[cnt_dn + i] = (T)bload<T>(xr, i * SZ, o_up);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
 
@@ -195,17 +219,18 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
         const uint32_t w[8] = {r0[0], r0[1], r0[2], r0[3], r1[0], r1[1], r1[2], r1[3]};
         const uint32_t L = w[0] & 0xffffu;
         const uint32_t t8 = t * SZ;
-        // every neighbour value first
+        // every neighbour value first: high-bit neighbours from memory, the
+        // low-bit ones from the staged segments
         double vl[B], vh[HF];
 #pragma unroll
+        for (int k = 0; k < HF; ++k) vh[k] = bload<T>(xr, t8, o_hi[k]);
+#pragma unroll
         for (int i = 0; i < B; ++i) {
-            // off[i] is the 16-bit field at byte 2 + 2 i
+            // off[i] is the 16-bit field at byte 2 + 2 i: byte offset in the staging area
             const uint32_t word = w[(2 + 2 * i) >> 2];
             const uint32_t off = ((2 + 2 * i) & 3) ? (word >> 16) : (word & 0xffffu);
-            vl[i] = bload<T>(xr, off, i < q ? o_dn : o_up);
+            vl[i] = (double)*(const T*)((const char*)stage + off);
         }
-#pragma unroll
-        for (int k = 0; k < HF; ++k) vh[k] = bload<T>(xr, t8, o_hi[k]);
         double A = 0.0, Bs = 0.0;
 #pragma unroll
         for (int i = 0; i < B; ++i) {
@@ -224,37 +249,31 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
         }
 #pragma unroll
         for (int k = 0; k < HF; ++k) {
-            A = fma(wlds[32 + k], vh[k], A);
-            if (MODE == S_PASS1) Bs = fma(wlds[48 + k], vh[k], Bs);
+            if (MODE == S_PASS1 && !((Tb >> k) & 1u))
+                Bs = fma(wlds[32 + k], vh[k], Bs);
+            else
+                A = fma(wlds[32 + k], vh[k], A);
         }
         // per-tile program terms: a busy unit u gains `rate` in the states
-        // whose low bits contain the term's mask
-        if (pmask != 0u) {
-            const uint32_t nL = ~L;
-            const uint32_t pstart = rl(rec, HQ_REC_PSTART);
-            const HQ_CONST ProgTerm* pg = cro(P.prog) + pstart;
-            uint32_t um = pmask;
-            while (um) {
-                const int u = __builtin_ctz(um);
-                um &= um - 1u;
-                const uint32_t i0 = rl(pov, u), i1 = rl(pov, u + 1);
-                double c = 0.0;
-                for (uint32_t i = i0; i < i1; ++i) {
-                    const uint32_t mk = pg[i].mask;
-                    const double rt = pg[i].rate;
-                    c += (mk & nL) == 0u ? rt : 0.0;
-                }
-                double v;
-                if (u < B) {
-                    // low unit: its down-neighbour L \ u, read again (0 weight when u is idle)
-                    const bool bz = (L >> u) & 1u;
-                    c = bz ? c : 0.0;
-                    v = bload<T>(xr, bz ? (uint32_t)s_rank[L ^ (1u << u)] * SZ : 0u, o_dn);
-                } else {
-                    v = bload<T>(xr, t8, rl(rec, HQ_REC_HI + (u - B)) * SZ - base * SZ);
-                }
-                A = fma(MODE == S_PASS1 ? c : s.wa * c, v, A);
+        // whose low bits contain the term's mask; the unit's neighbour value
+        // is read again (a high unit's from memory, where it was just read; a
+        // low unit's, only where it is busy, from the staging area)
+        const uint32_t nL = ~L;
+        uint32_t um = pmask;
+        while (um) {
+            const int u = __builtin_ctz(um);
+            um &= um - 1u;
+            double c = unit_terms(pg, pov, tmk, trt, u, nL);
+            double v;
+            if (u < B) {
+                const bool bz = (L >> u) & 1u;
+                const uint32_t rk = bz ? (uint32_t)s_rank[L ^ (1u << u)] : 0u;
+                v = (double)stage[rk];
+                c = bz ? c : 0.0;
+            } else {
+                v = bload<T>(xr, t8, (rl(rec, HQ_REC_HI + (u - B)) - base) * SZ);
             }
+            A = fma(MODE == S_PASS1 ? c : s.wa * c, v, A);
         }
         const double mu_m = mu_hi + mu_lo;
         const double inv = recip(den_hi + mu_lo);
@@ -283,16 +302,23 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
             const double ps = (double)stored * s.is_self;
             acc0 += ps;
             acc1 = fma(mu_m, ps, acc1);
+            if (la_w) {
+                // look-ahead closed form: the sums the next layers' alpha needs
+                const uint32_t o64 = rl(rec, HQ_REC_SELF) + t;
+                acc4 = fma(ps, la_w[o64], acc4);
+                acc5 = fma(ps, la_z[o64], acc5);
+            }
         }
     }
 }
 
 template <typename T, int MODE, bool TRACK, int HF>
-__global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(5, 8))) void sweep_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
+__global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(MODE == S_PASS1 ? 4 : 5, 8))) void sweep_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
                                                       int inner_one) {
     __shared__ double s_w[WAVES * 64];
+    __shared__ T s_stage[WAVES][HQ_SWEEP_STAGE];  // per wave: segments (T, q - 1) and (T, q + 1)
     __shared__ uint16_t s_rank[1 << B];
-    __shared__ double s_red[4][WAVES];
+    __shared__ double s_red[HQ_NPART][WAVES];
     const int tid = threadIdx.x, lane = tid & 63;
     for (int i = tid; i < (1 << B); i += HQ_WG) s_rank[i] = P.lo_rank[i];
     __syncthreads();
@@ -304,7 +330,9 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     const LowRow* rows = sizeof(T) == 8 ? P.lrow : P.lrow32;
     const __amdgpu_buffer_rsrc_t rowr = __builtin_amdgcn_make_buffer_rsrc(const_cast<LowRow*>(rows), 0,
                                                                           (1 << B) * (int)sizeof(LowRow), RSRC_W3);
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0, acc5 = 0.0;
+    const double* la_w = MODE == S_WRITE ? P.la_w : nullptr;
+    const double* la_z = MODE == S_WRITE ? P.la_z : nullptr;
     // wave-granular segments; the eight XCDs sweep contiguous eighths
     const uint32_t G = gridDim.x, wg = blockIdx.x;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -327,29 +355,38 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     auto load_rec = [&](uint32_t si) -> uint32_t {
         return (si < end && lane < HQ_REC_WORDS) ? recs[(size_t)si * HQ_REC_WORDS + lane] : 0u;
     };
-    auto load_tile = [&](uint32_t si, uint32_t rec, double& tcv, uint32_t& pov) {
-        tcv = 0.0;
-        pov = 0u;
-        if (si >= end) return;
-        const uint32_t Tb = rl(rec, HQ_REC_DESC) >> 4;
-        if (lane < P.N) tcv = P.tcoef[(size_t)Tb * P.N + lane];
-        if (rl(rec, HQ_REC_PMASK) != 0u && lane <= P.N)
-            pov = P.prog_off[(size_t)Tb * (P.N + 1) + lane] - rl(rec, HQ_REC_PSTART);
+    // tile data of a segment, lane-parallel: lane u its tile coefficient and
+    // first program term, lane i the mask and rate of program term i < 64
+    struct Tile {
+        double tcv, trt;
+        uint32_t pov, tmk;
     };
+    auto load_tile = [&](uint32_t si, uint32_t rec) -> Tile {
+        Tile tl{0.0, 0.0, 0u, 0u};
+        if (si >= end) return tl;
+        const uint32_t Tb = rl(rec, HQ_REC_DESC) >> 4;
+        if (lane < P.N) tl.tcv = P.tcoef[(size_t)Tb * P.N + lane];
+        if (rl(rec, HQ_REC_PMASK) != 0u) {
+            const uint32_t pstart = rl(rec, HQ_REC_PSTART), pcount = rl(rec, HQ_REC_PCOUNT);
+            if (lane <= P.N) tl.pov = P.prog_off[(size_t)Tb * (P.N + 1) + lane] - pstart;
+            if ((uint32_t)lane < pcount) {
+                tl.tmk = P.prog[pstart + lane].mask;
+                tl.trt = P.prog[pstart + lane].rate;
+            }
+        }
+        return tl;
+    };
+    T* stage = s_stage[wv];
     uint32_t rec0 = load_rec(begin), rec1 = load_rec(begin + step);
-    double tc0;
-    uint32_t pov0;
-    load_tile(begin, rec0, tc0, pov0);
+    Tile t0 = load_tile(begin, rec0);
     for (uint32_t si = begin; si < end; si += step) {
         const uint32_t rec2 = load_rec(si + 2 * step);
-        double tc1;
-        uint32_t pov1;
-        load_tile(si + step, rec1, tc1, pov1);
-        segment<T, MODE, TRACK, HF>(P, xr, rowr, base, rec0, tc0, pov0, s, wlds, s_rank, acc0, acc1, acc2, acc3);
+        const Tile t1 = load_tile(si + step, rec1);
+        segment<T, MODE, TRACK, HF>(P, xr, rowr, base, rec0, t0.tcv, t0.pov, t0.tmk, t0.trt, s, wlds, stage, s_rank,
+                                    acc0, acc1, acc2, acc3, acc4, acc5, la_w, la_z);
         rec0 = rec1;
         rec1 = rec2;
-        tc0 = tc1;
-        pov0 = pov1;
+        t0 = t1;
     }
     // work-group partials (sum, sum, max, max); the finalize launch adds
     // them in a fixed order
@@ -357,26 +394,29 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     acc1 = wave_sum(acc1);
     acc2 = wave_max(acc2);
     acc3 = wave_max(acc3);
+    acc4 = wave_sum(acc4);
+    acc5 = wave_sum(acc5);
     if (lane == 0) {
         s_red[0][wv] = acc0;
         s_red[1][wv] = acc1;
         s_red[2][wv] = acc2;
         s_red[3][wv] = acc3;
+        s_red[4][wv] = acc4;
+        s_red[5][wv] = acc5;
     }
     __syncthreads();
     if (tid == 0) {
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+        double b[HQ_NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int i = 0; i < WAVES; ++i) {
-            b0 += s_red[0][i];
-            b1 += s_red[1][i];
-            b2 = fmax(b2, s_red[2][i]);
-            b3 = fmax(b3, s_red[3][i]);
+            b[0] += s_red[0][i];
+            b[1] += s_red[1][i];
+            b[2] = fmax(b[2], s_red[2][i]);
+            b[3] = fmax(b[3], s_red[3][i]);
+            b[4] += s_red[4][i];
+            b[5] += s_red[5][i];
         }
         double* pp = P.partials + (size_t)blockIdx.x * HQ_NPART;
-        pp[0] = b0;
-        pp[1] = b1;
-        pp[2] = b2;
-        pp[3] = b3;
+        for (int j = 0; j < HQ_NPART; ++j) pp[j] = b[j];
     }
 }
 

@@ -28,11 +28,13 @@
 
 // Per low pattern, in the order of lo_unrank (class q, then colex rank t):
 // the pattern; for its q set bits (increasing) the byte offset of L minus
-// that bit inside segment (T, q - 1), then for its b - q clear bits the
-// byte offset of L plus that bit inside (T, q + 1) (one table per element
-// size); the byte offset of each entry's weight in a wave's 64-double LDS
-// area (unit l of a set bit: l, of a clear bit: 16 + l); and the
-// service-rate sum of the pattern's units.
+// that bit in a wave's staging area, which holds segment (T, q - 1) and
+// then segment (T, q + 1); then for its b - q clear bits the byte offset of
+// L plus that bit there (one table per element size); the byte offset of
+// each entry's weight in a wave's 64-double LDS area (unit l of a set bit:
+// l, of a clear bit: 16 + l); and the service-rate sum of the pattern's
+// units.
+#define HQ_SWEEP_STAGE 424  // staging elements per wave: >= C(10, q - 1) + C(10, q + 1) for every q
 struct LowRow {
     uint16_t L;
     uint16_t off[HQ_SWEEP_B];
@@ -44,9 +46,10 @@ static_assert(sizeof(LowRow) == 40, "LowRow is read as 40-byte rows");
 namespace hqsweeptab {
 
 // Rows of the low patterns in lo_unrank order (class q, then colex rank):
-// set bits first (down-neighbour L minus the bit in class q - 1, weight
-// slot l), then clear bits (up-neighbour L plus the bit in class q + 1,
-// weight slot 16 + l); `elem` is the element size the offsets count in.
+// set bits first (down-neighbour L minus the bit at its rank in class
+// q - 1, weight slot l), then clear bits (up-neighbour L plus the bit at
+// C(b, q - 1) + its rank in class q + 1, weight slot 16 + l); `elem` is
+// the element size the offsets count in.
 inline std::vector<LowRow> low_rows(const hqlayout::Layout& lay, const std::vector<double>& nu, int elem) {
     const int b = lay.b;
     const uint32_t lo = 1u << b;
@@ -63,7 +66,9 @@ inline std::vector<LowRow> low_rows(const hqlayout::Layout& lay, const std::vect
             }
         for (int l = 0; l < b; ++l)
             if (!((L >> l) & 1u)) {
-                r.off[k] = (uint16_t)(lay.lo_rank[L | (1u << l)] * (uint32_t)elem);
+                const int q = __builtin_popcount(L);
+                const uint32_t dn = q > 0 ? (uint32_t)hqlayout::binom(b, q - 1) : 0u;
+                r.off[k] = (uint16_t)((dn + lay.lo_rank[L | (1u << l)]) * (uint32_t)elem);
                 r.slot[k++] = (uint8_t)(8 * (16 + l));
             }
         double m = 0.0;

@@ -6,8 +6,9 @@
 //   - self + t is the position of m = (T << b) | L;
 //   - for a row entry k < q: unit l = slot / 8 is set in L (entries in
 //     increasing l) and dn + off / elem is the position of m minus unit l;
-//   - for k >= q: unit l = slot / 8 - 16 is clear in L and up + off / elem is
-//     the position of m plus unit l;
+//   - for k >= q: unit l = slot / 8 - 16 is clear in L and
+//     up + off / elem - C(b, q - 1) is the position of m plus unit l (a
+//     wave's staging area holds the down segment, then the up segment);
 //   - hi[k] + t is the position of m xor 2^(b + k);
 //   - mu_lo and mu_hi are the service-rate sums of the busy units, pmask
 //     marks the units with program terms and pstart/pcount the tile's terms.
@@ -107,9 +108,12 @@ int main(int argc, char** argv) {
                             CHECK(l >= 0 && l < b && !((L >> l) & 1u), "up entry %d of L=%u", k, L);
                             CHECK(l > prev, "order");
                             prev = l;
-                            CHECK(w[HQ_REC_UP] + e / elem == position(m | (1u << l), lay.layer_off),
+                            const uint32_t dn = q > 0 ? (uint32_t)hqlayout::binom(b, q - 1) : 0u;
+                            CHECK(e / elem >= dn, "up offset after the down segment");
+                            CHECK(w[HQ_REC_UP] + (e / elem - dn) == position(m | (1u << l), lay.layer_off),
                                   "up neighbour of m=%u unit %d", m, l);
-                            CHECK(e / elem < hqlayout::binom(b, q + 1), "up offset in segment");
+                            CHECK(e / elem - dn < hqlayout::binom(b, q + 1), "up offset in segment");
+                            CHECK(e / elem < HQ_SWEEP_STAGE, "staging area");
                         }
                     }
                     CHECK(std::fabs(ml - r.mu_lo) <= 1e-12, "mu_lo");

@@ -280,3 +280,59 @@ def test_default_shape_sweep_matches_general_kernels(inner, prec, monkeypatch):
         assert ra == pytest.approx(rb, rel=1e-9 if prec == "fp64" else 1e-5)
     hq.hq_destroy(new)
     hq.hq_destroy(old)
+
+
+@pytest.mark.parametrize("inner", ["one", "closed", "literal"])
+def test_graph_replays_match_eager_launches(inner, monkeypatch):
+    """An outer iteration is captured once as a graph of kernel launches and
+    replayed: after every replay, with exports, residual checks and
+    synchronisations in between, the iterate is bitwise the one of eager
+    launches."""
+    inst = config_instance(3, 3, N=17, J=150)
+    say(f"case graph replays inner={inner}")
+    kw = dict(inner=INNER[inner], delta=1e-6)
+    g = _gpu(inst, **kw)
+    monkeypatch.setenv("HQ_NO_GRAPH", "1")
+    e = _gpu(inst, **kw)
+    monkeypatch.delenv("HQ_NO_GRAPH")
+    for k in range(6):
+        hq.hq_iterate(g, 1)
+        hq.hq_iterate(e, 1)
+        a, b = hq.hq_conditional(g), hq.hq_conditional(e)
+        assert np.array_equal(a, b), f"replay {k}"
+        assert hq.hq_residual(g) == hq.hq_residual(e)
+    # a full solve through the graphs reaches the same answer
+    ig, ie = hq.hq_solve(g, 1e-11), hq.hq_solve(e, 1e-11)
+    assert ig["iterations"] == ie["iterations"]
+    assert np.array_equal(hq.hq_state(g), hq.hq_state(e))
+    hq.hq_destroy(g)
+    hq.hq_destroy(e)
+
+
+@pytest.mark.parametrize("stored", [-1, 4])
+def test_lookahead_closed_form_matches_two_passes_and_oracle(stored, monkeypatch):
+    """The closed inner form in one pass per layer: the sums behind alpha_n
+    (sum U~ and sum mu D~ over layer n) are re-indexed over layers n - 1 and
+    n + 1 and accumulated while those layers are written.  Same iterate as
+    the two-pass form (to rounding) and as the oracle's closed-form path;
+    with stored coefficient layers too."""
+    inst = config_instance(2, 21, N=17, J=120)
+    say(f"case look-ahead closed N=17 stored={stored}")
+    la = _gpu(inst, inner=hq.HQ_INNER_CLOSED, stored_layers=stored)
+    monkeypatch.setenv("HQ_NO_LOOKAHEAD", "1")
+    two = _gpu(inst, inner=hq.HQ_INNER_CLOSED, stored_layers=stored)
+    monkeypatch.delenv("HQ_NO_LOOKAHEAD")
+    done = 0
+    for k in (1, 2, 5):
+        hq.hq_iterate(la, k - done)
+        hq.hq_iterate(two, k - done)
+        done = k
+        a, b = hq.hq_conditional(la), hq.hq_conditional(two)
+        assert _rel_close(a, b, 1e-12) == 0, f"k={k}"
+        ref = cpu.solve(inst, tol=0.0, max_iters=k, inner="closed")
+        assert _rel_close(a, ref.pcond, 1e-11) == 0, f"k={k} vs oracle"
+    ia, ib = hq.hq_solve(la, 1e-11), hq.hq_solve(two, 1e-11)
+    assert abs(ia["iterations"] - ib["iterations"]) <= 1
+    assert np.abs(hq.hq_state(la) - hq.hq_state(two)).sum() <= 1e-12
+    hq.hq_destroy(la)
+    hq.hq_destroy(two)
