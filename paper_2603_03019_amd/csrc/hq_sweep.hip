@@ -426,27 +426,51 @@ namespace hqk {
 
 using namespace hqsweep;
 
+// Work-groups of one launch: every wave owns whole segments, and the grid
+// never exceeds what the device holds at once (the kernel's occupancy times
+// the compute units), so no work-group waits for another to finish before
+// it starts its share; a multiple of 8 when large (XCD-chunked order).
+template <typename T, int MODE, bool TRACK, int HF>
+static uint32_t resident_groups() {
+    static const uint32_t r = [] {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_kernel<T, MODE, TRACK, HF>, HQ_WG, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        (void)hipGetLastError();
+        return (uint32_t)(per_cu * cus);
+    }();
+    return r;
+}
+
+template <typename T, int MODE, bool TRACK, int HF>
 static uint32_t sweep_grid(uint32_t groups) {
     const uint32_t wgs = (groups + WAVES - 1) / WAVES;
     if (wgs < 64) return wgs > 0 ? wgs : 1;
-    uint32_t g = wgs < HQ_GRID ? wgs : HQ_GRID;
-    return g & ~7u;
+    const uint32_t cap = resident_groups<T, MODE, TRACK, HF>();
+    uint32_t g = wgs < cap ? wgs : cap;
+    return g >= 8 ? g & ~7u : g;
+}
+
+template <typename T, int MODE, bool TRACK, int HF>
+static uint32_t launch_one(const SweepParams& P, const LayerArgs& A, T* x, int inner_one, hipStream_t s) {
+    const uint32_t g = sweep_grid<T, MODE, TRACK, HF>(A.groups);
+    hipLaunchKernelGGL((sweep_kernel<T, MODE, TRACK, HF>), dim3(g), dim3(HQ_WG), 0, s, P, A, x, inner_one);
+    return g;
 }
 
 template <typename T, int HF>
-static void launch_h(int mode, bool track, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
-                     hipStream_t s) {
-    dim3 grid(sweep_grid(A.groups)), block(HQ_WG);
-    if (mode == 1 /* M_WRITE */ && !track)
-        hipLaunchKernelGGL((sweep_kernel<T, S_WRITE, false, HF>), grid, block, 0, s, P, A, x, inner_one);
-    else if (mode == 1)
-        hipLaunchKernelGGL((sweep_kernel<T, S_WRITE, true, HF>), grid, block, 0, s, P, A, x, inner_one);
-    else if (mode == 0 /* M_PASS1 */ && track)
-        hipLaunchKernelGGL((sweep_kernel<T, S_PASS1, true, HF>), grid, block, 0, s, P, A, x, inner_one);
-    else if (mode == 0)
-        hipLaunchKernelGGL((sweep_kernel<T, S_PASS1, false, HF>), grid, block, 0, s, P, A, x, inner_one);
-    else
-        hipLaunchKernelGGL((sweep_kernel<T, S_RESID, false, HF>), grid, block, 0, s, P, A, x, inner_one);
+static uint32_t launch_h(int mode, bool track, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
+                         hipStream_t s) {
+    if (mode == 1 /* M_WRITE */ && !track) return launch_one<T, S_WRITE, false, HF>(P, A, x, inner_one, s);
+    if (mode == 1) return launch_one<T, S_WRITE, true, HF>(P, A, x, inner_one, s);
+    if (mode == 0 /* M_PASS1 */ && track) return launch_one<T, S_PASS1, true, HF>(P, A, x, inner_one, s);
+    if (mode == 0) return launch_one<T, S_PASS1, false, HF>(P, A, x, inner_one, s);
+    return launch_one<T, S_RESID, false, HF>(P, A, x, inner_one, s);
 }
 
 // Launch the sweep kernel of layer A.n for the default tile shape; returns
@@ -456,13 +480,10 @@ static void launch_h(int mode, bool track, const SweepParams& P, const LayerArgs
 uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
                       int inner_one, hipStream_t s) {
     if (P.b != B || A.stored || !P.srec || !P.lrow || A.n < 1 || A.n >= P.N) return 0;
-#define HQ_SW(HV)                                                              \
-    case HV:                                                                   \
-        if (fp32)                                                              \
-            launch_h<float, HV>(mode, track, P, A, (float*)x, inner_one, s);   \
-        else                                                                   \
-            launch_h<double, HV>(mode, track, P, A, (double*)x, inner_one, s); \
-        break;
+#define HQ_SW(HV)                                                                     \
+    case HV:                                                                          \
+        return fp32 ? launch_h<float, HV>(mode, track, P, A, (float*)x, inner_one, s) \
+                    : launch_h<double, HV>(mode, track, P, A, (double*)x, inner_one, s);
     switch (P.H) {
         HQ_SW(6) HQ_SW(7) HQ_SW(8) HQ_SW(9) HQ_SW(10) HQ_SW(11) HQ_SW(12) HQ_SW(13) HQ_SW(14) HQ_SW(15)
         HQ_SW(16) HQ_SW(17) HQ_SW(18) HQ_SW(19) HQ_SW(20)
@@ -470,7 +491,6 @@ uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, con
             return 0;
     }
 #undef HQ_SW
-    return sweep_grid(A.groups);
 }
 
 }  // namespace hqk

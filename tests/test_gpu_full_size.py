@@ -221,3 +221,58 @@ def test_full_size_converged_balance_and_marginals(big):
     np.testing.assert_allclose(pn, rp, rtol=1e-9, atol=1e-300)
     # flow balance per unit: sum_u nu_u rho_u = Lambda (1 - P(full))
     assert (inst.nu * rho).sum() == pytest.approx(inst.Lambda * (1 - P[-1]), rel=1e-7)
+
+
+def _read_reference(path):
+    ref = {"pn": {}, "rho": {}, "heavy": [], "flat": []}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, *v = line.split()
+            if k in ("pn", "rho"):
+                ref[k][int(v[0])] = float(v[1])
+            elif k in ("heavy", "flat"):
+                ref[k].append((int(v[0]), float(v[1])))
+            else:
+                ref[k] = v[0]
+    return ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "polish"])
+def test_full_size_converged_answer_matches_oracle_reference(big, precision):
+    """The converged N = 26 answer against the oracle's own converged answer
+    (tests/golden/n26_oracle.txt, written by make_n26_reference.py from an
+    hour-long oracle solve to a 1e-12 balance residual): the number-busy
+    marginal p(n) and the busy probabilities rho_u, and P at 4096 states
+    drawn with probability P (the mean of |dP| / P over them estimates the
+    L1 distance) and 4096 drawn uniformly."""
+    import os
+
+    inst = big[0]
+    ref = _read_reference(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "n26_oracle.txt"))
+    assert int(ref["N"]) == inst.N
+    say(f"case N=26 converged vs oracle reference ({precision})")
+    p = hq.HQ_FP32_POLISH64 if precision == "polish" else hq.HQ_FP64
+    ctx = hq.create_from_instance(inst, inner=hq.HQ_INNER_ONE, precision=p)
+    info = hq.hq_solve(ctx, 1e-12)
+    rho, pn = hq.hq_marginals(ctx)
+    P = hq.hq_state(ctx)
+    hq.hq_destroy(ctx)
+    pn_ref = np.array([ref["pn"][n] for n in range(inst.N + 1)])
+    rho_ref = np.array([ref["rho"][u] for u in range(inst.N)])
+    hm = np.array([m for m, _ in ref["heavy"]], dtype=np.int64)
+    hv = np.array([v for _, v in ref["heavy"]])
+    fm = np.array([m for m, _ in ref["flat"]], dtype=np.int64)
+    fv = np.array([v for _, v in ref["flat"]])
+    rel_h = np.abs(P[hm] - hv) / hv
+    rel_f = np.abs(P[fm] - fv) / fv
+    l1_est = float(rel_h.mean())
+    mpre = 100.0 * float(max(rel_h.max(), rel_f.max()))
+    say(f"  {info['iterations']} iterations, residual {info['residual']:.2e}; max |dp(n)| "
+        f"{np.abs(pn - pn_ref).max():.2e}, max |drho| {np.abs(rho - rho_ref).max():.2e}, L1 estimate "
+        f"{l1_est:.2e}, MPRE over the sampled states {mpre:.2e} %")
+    assert np.abs(pn - pn_ref).max() <= 1e-10
+    assert np.abs(rho - rho_ref).max() <= 1e-10
+    assert l1_est <= 1e-10
+    assert rel_f.max() <= 1e-8
