@@ -28,10 +28,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 L1 residual & state-updates/s at N=26; warm/batched vs plain"
 HBM_PEAK_GBS = 8000.0
-# sources that decide what the sweep launches do: the kernels, and the host
-# code that builds the dispatch programs and picks the stored layers
+# sources that decide what the sweep launches do: the kernels, their tables,
+# and the host code that builds the dispatch programs and picks the stored
+# layers
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_03019_amd", "csrc", f)
-               for f in ("hq_kernels.hip", "hq_api.cpp", "hq_tables.h", "hq_layout.h")]
+               for f in ("hq_kernels.hip", "hq_sweep.hip", "hq_sweeptab.h", "hq_api.cpp", "hq_tables.h",
+                         "hq_layout.h")]
 
 
 def kernel_source_hash() -> str:
@@ -254,6 +256,8 @@ def fp32_leg(hq, inst, tol: float, P64, steps: int):
         "sweep_state_updates_per_s": ((1 << inst.N) - 2) * it["iterations"] / max(it["sweep_seconds"], 1e-12),
         "final_residual": it["residual"],
         "l1_vs_fp64": float(np.abs(P - P64).sum()),
+        # maximum percentage relative error over the states, eq. (15)
+        "mpre_vs_fp64_percent": float(100.0 * np.max(np.abs(P - P64)[P64 > 0] / P64[P64 > 0])),
     }
 
 
@@ -360,7 +364,6 @@ def main():
     states = (1 << inst.N) - 2
     s = 8 if args.precision == "fp64" else 4
     bytes_it = algorithmic_bytes_per_iteration(inst.N, s)
-    passes = 2 if args.inner == "closed" else 1
     per_it = sweep_s / max(iters, 1)
     achieved = bytes_it / per_it / 1e9
     out = {
@@ -395,8 +398,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(inst.N, args.precision),
-            "kernel": f"layer_kernel (M_WRITE{' + M_PASS1' if passes == 2 else ''}), per outer iteration "
-                      f"of {inst.N - 1} layer launches",
+            "kernel": "layer sweep: sweep_kernel (computed-coefficient layers) and layer_kernel (stored "
+                      f"layers){' with the look-ahead sums of the closed form' if args.inner == 'closed' else ''}, per outer "
+                      f"iteration of {inst.N - 1} layer launches and their finalize launches",
             "bytes_per_iteration": bytes_it,
             "us_per_iteration": per_it * 1e6,
         },

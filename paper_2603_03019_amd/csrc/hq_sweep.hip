@@ -27,10 +27,14 @@
 // Weights.  Per segment, lane u forms the weight of unit u in the combined
 // sum: alpha-side (tile coefficient of a busy unit, eq. (3) / Algorithm 3)
 // or beta-side (service rate of an idle unit), with the layer scalars and
-// storage scales folded in.  High units' weights are broadcast to scalar
-// registers; low units' weights go to a per-wave LDS slot and are read by
-// the lane's entry.  Per-tile program terms (busy units whose coefficient
-// depends on low bits) are added for the units the record marks.
+// storage scales folded in.  All weights go to a per-wave LDS slot: a
+// high unit's is read as a broadcast, a low unit's by the lane's entry.
+// Per-tile program terms (busy units whose coefficient depends on low
+// bits) are added for the units the record marks, each unit's terms summed
+// first and multiplied once by its neighbour value: a high unit's value is
+// still in registers (the first two such units get a second copy loaded
+// next to the others, the rest are selected from the loaded set), a low
+// unit's is read again from the staging area.
 //
 // Arithmetic is FP64 throughout; with FP32 storage the neighbour values are
 // widened on load and the written value rounded once.
@@ -50,7 +54,9 @@ constexpr int B = HQ_SWEEP_B;  // low bits per tile
 constexpr int WAVES = HQ_WG / 64;
 constexpr int RSRC_W3 = 0x00020000;  // buffer resource word 3 on gfx9 (32-bit data format, raw)
 
-enum { S_WRITE = 0, S_PASS1 = 1, S_RESID = 2 };
+// S_WRITE_LA: the sweep of the closed inner form, which also accumulates
+// the look-ahead sums of the next layers' alpha
+enum { S_WRITE = 0, S_PASS1 = 1, S_RESID = 2, S_WRITE_LA = 3 };
 
 __device__ __forceinline__ uint32_t rl(uint32_t v, int i) { return (uint32_t)__builtin_amdgcn_readlane((int)v, i); }
 __device__ __forceinline__ double rld(double v, int i) {
@@ -117,7 +123,7 @@ __device__ __forceinline__ Scal load_scal(const SweepParams& P, int n, int inner
         const double alpha0 = P.sc.mu[n] / P.sc.lam[n - 1];  // mu^{k-1}(n) / lambda^k(n-1)
         s.alpha0 = alpha0;
         s.beta0 = beta;
-        if (MODE == S_WRITE) {
+        if (MODE == S_WRITE || MODE == S_WRITE_LA) {
             const double alpha = inner_one == 1 ? alpha0 : P.sc.alpha[n];
             const double s_self = P.scale[n];
             s.wa = alpha * is_dn * s_self;
@@ -131,26 +137,39 @@ __device__ __forceinline__ Scal load_scal(const SweepParams& P, int n, int inner
     return s;
 }
 
-// Sum of the rates of unit u's program terms whose low mask lies in L (the
-// terms of the segment's tile: the first 64 held lane-parallel, mask in tmk
-// and rate in trt, the rest read as scalar loads).
+// Sum of the rates of unit u's program terms whose low mask lies in L (nL
+// = ~L).  The tile's first 64 terms are held lane-parallel (mask in tmk,
+// rate in trt); terms past 64 are read as scalar loads.
 __device__ __forceinline__ double unit_terms(const HQ_CONST ProgTerm* pg, uint32_t pov, uint32_t tmk, double trt,
                                              int u, uint32_t nL) {
     const uint32_t i0 = rl(pov, u), i1 = rl(pov, u + 1);
+    const uint32_t ir = i1 < 64u ? i1 : 64u;
     double c = 0.0;
-    for (uint32_t i = i0; i < i1; ++i) {
-        uint32_t mk;
-        double rt;
-        if (i < 64) {
-            mk = rl(tmk, (int)i);
-            rt = rld(trt, (int)i);
-        } else {
-            mk = pg[i].mask;
-            rt = pg[i].rate;
-        }
+    for (uint32_t i = i0; i < ir; ++i) {
+        const uint32_t mk = rl(tmk, (int)i);
+        const double rt = rld(trt, (int)i);
+        c += (mk & nL) == 0u ? rt : 0.0;
+    }
+    for (uint32_t i = i0 > 64u ? i0 : 64u; i < i1; ++i) {
+        const uint32_t mk = pg[i].mask;
+        const double rt = pg[i].rate;
         c += (mk & nL) == 0u ? rt : 0.0;
     }
     return c;
+}
+
+// vh[k] for a wave-uniform k, by a chain of selects (the values stay in
+// registers; no indexed private array, no memory round trip).
+template <int HF>
+__device__ __forceinline__ double pick(const double (&vh)[HF], int k) {
+    double v = vh[0];
+#pragma unroll
+    for (int j = 1; j < HF; ++j) {
+        v = k == j ? vh[j] : v;
+        // keeps the chain a chain of selects (not an indexed private array)
+        asm volatile("" : "+v"(v));
+    }
+    return v;
 }
 
 // One wave, one segment.  HF = H (high bits), fixed at compile time.
@@ -182,6 +201,14 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
     const uint32_t cnt_up = q < B ? cro(P.binom)[B * 32 + q + 1] : 0u;
     const uint32_t qs = cro(P.lo_qstart)[q];
     const uint32_t pmask = rl(rec, HQ_REC_PMASK);
+    // the first two high units with program terms: their neighbour values
+    // are loaded a second time, next to the others, for the term step
+    const uint32_t hm = pmask >> B;
+    const int k0 = hm ? __builtin_ctz(hm) : -1;
+    const uint32_t hm1 = hm & (hm - 1u);
+    const int k1 = hm1 ? __builtin_ctz(hm1) : -1;
+    const uint32_t o_t0 = k0 >= 0 ? (rl(rec, HQ_REC_HI + k0) - base) * SZ : o_self;
+    const uint32_t o_t1 = k1 >= 0 ? (rl(rec, HQ_REC_HI + k1) - base) * SZ : o_self;
     const HQ_CONST ProgTerm* pg = cro(P.prog) + rl(rec, HQ_REC_PSTART);
     // weights: lane u < N holds unit u's; alpha-side for busy units (tile
     // coefficient), beta-side for idle ones (service rate)
@@ -224,6 +251,14 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
         double vl[B], vh[HF];
 #pragma unroll
         for (int k = 0; k < HF; ++k) vh[k] = bload<T>(xr, t8, o_hi[k]);
+        const double vt0 = bload<T>(xr, t8, o_t0), vt1 = bload<T>(xr, t8, o_t1);
+        // look-ahead weights of this state (closed form), in flight with the rest
+        double lw = 0.0, lz = 0.0;
+        if (MODE == S_WRITE_LA) {
+            const uint32_t o64 = rl(rec, HQ_REC_SELF) + t;
+            lw = la_w[o64];
+            lz = la_z[o64];
+        }
 #pragma unroll
         for (int i = 0; i < B; ++i) {
             // off[i] is the 16-bit field at byte 2 + 2 i: byte offset in the staging area
@@ -270,8 +305,12 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
                 const uint32_t rk = bz ? (uint32_t)s_rank[L ^ (1u << u)] : 0u;
                 v = (double)stage[rk];
                 c = bz ? c : 0.0;
+            } else if (u - B == k0) {
+                v = vt0;
+            } else if (u - B == k1) {
+                v = vt1;
             } else {
-                v = bload<T>(xr, t8, (rl(rec, HQ_REC_HI + (u - B)) - base) * SZ);
+                v = pick<HF>(vh, u - B);
             }
             A = fma(MODE == S_PASS1 ? c : s.wa * c, v, A);
         }
@@ -302,11 +341,10 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
             const double ps = (double)stored * s.is_self;
             acc0 += ps;
             acc1 = fma(mu_m, ps, acc1);
-            if (la_w) {
+            if (MODE == S_WRITE_LA) {
                 // look-ahead closed form: the sums the next layers' alpha needs
-                const uint32_t o64 = rl(rec, HQ_REC_SELF) + t;
-                acc4 = fma(ps, la_w[o64], acc4);
-                acc5 = fma(ps, la_z[o64], acc5);
+                acc4 = fma(ps, lw, acc4);
+                acc5 = fma(ps, lz, acc5);
             }
         }
     }
@@ -331,8 +369,8 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(MODE == S
     const __amdgpu_buffer_rsrc_t rowr = __builtin_amdgcn_make_buffer_rsrc(const_cast<LowRow*>(rows), 0,
                                                                           (1 << B) * (int)sizeof(LowRow), RSRC_W3);
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0, acc5 = 0.0;
-    const double* la_w = MODE == S_WRITE ? P.la_w : nullptr;
-    const double* la_z = MODE == S_WRITE ? P.la_z : nullptr;
+    const double* la_w = MODE == S_WRITE_LA ? P.la_w : nullptr;
+    const double* la_z = MODE == S_WRITE_LA ? P.la_z : nullptr;
     // wave-granular segments; the eight XCDs sweep contiguous eighths
     const uint32_t G = gridDim.x, wg = blockIdx.x;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -466,7 +504,8 @@ static uint32_t launch_one(const SweepParams& P, const LayerArgs& A, T* x, int i
 template <typename T, int HF>
 static uint32_t launch_h(int mode, bool track, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
                          hipStream_t s) {
-    if (mode == 1 /* M_WRITE */ && !track) return launch_one<T, S_WRITE, false, HF>(P, A, x, inner_one, s);
+    if (mode == 1 /* M_WRITE */ && P.la_w) return track ? 0u : launch_one<T, S_WRITE_LA, false, HF>(P, A, x, inner_one, s);
+    if (mode == 1 && !track) return launch_one<T, S_WRITE, false, HF>(P, A, x, inner_one, s);
     if (mode == 1) return launch_one<T, S_WRITE, true, HF>(P, A, x, inner_one, s);
     if (mode == 0 /* M_PASS1 */ && track) return launch_one<T, S_PASS1, true, HF>(P, A, x, inner_one, s);
     if (mode == 0) return launch_one<T, S_PASS1, false, HF>(P, A, x, inner_one, s);
@@ -476,7 +515,8 @@ static uint32_t launch_h(int mode, bool track, const SweepParams& P, const Layer
 // Launch the sweep kernel of layer A.n for the default tile shape; returns
 // the number of work-groups (whose partials the finalize launch reads), or
 // 0 when this shape or layer is not covered (stored coefficients, another
-// tile width, the end layers of the residual).
+// tile width, the end layers of the residual, the closed form's sweep with
+// the paper's delta tracking).
 uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
                       int inner_one, hipStream_t s) {
     if (P.b != B || A.stored || !P.srec || !P.lrow || A.n < 1 || A.n >= P.N) return 0;
