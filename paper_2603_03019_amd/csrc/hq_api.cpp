@@ -41,7 +41,7 @@ hipError_t launch_dispatch(double* G, int N, int J, const int32_t* pref, double*
 hipError_t launch_widen(const float* src, double* dst, uint32_t begin, uint32_t count, double factor,
                         hipStream_t s);
 hipError_t launch_coef(const SweepParams& P, const LayerArgs& A, double* coefs, uint32_t nnodes, hipStream_t s);
-hipError_t launch_lookahead(const SweepParams& P, const LayerArgs& A, double* w, double* z, uint32_t nnodes,
+hipError_t launch_lookahead(const SweepParams& P, const LayerArgs& A, double* wz, uint32_t nnodes,
                             hipStream_t s);
 hipError_t launch_batch(bool fp32, int block, const BatchItem* items, const BatchEntry* entries, BatchOut* outs,
                         int count, unsigned int* next, unsigned int* group_counts, int n_items, int grid,
@@ -142,7 +142,7 @@ struct hq_ctx {
     uint16_t *d_lo_unrank = nullptr, *d_lo_rank = nullptr;
     TrieNode* d_nodes = nullptr;
     unsigned int* d_counters = nullptr;
-    double* d_la = nullptr;      // look-ahead closed form: w(l), then z(l), per state (2 * 2^N)
+    double* d_la = nullptr;      // look-ahead closed form: (w(l), z(l)) per state, interleaved (2 * 2^N)
     uint32_t* d_srec = nullptr;  // segment records of the default-shape sweep
     LowRow* d_lrow = nullptr;    // its low-pattern rows (FP64 offsets)
     LowRow* d_lrow32 = nullptr;  // and with FP32 offsets
@@ -288,8 +288,7 @@ void setup_params(hq_ctx* c) {
     P.sc.misc = c->d_scal + 7 * L;
     P.sc.wsum = c->d_scal + 8 * L + 8;
     P.sc.zsum = c->d_scal + 9 * L + 8;
-    P.la_w = c->d_la;
-    P.la_z = c->d_la ? c->d_la + c->states() : nullptr;
+    P.la = c->d_la;
     P.srec = c->d_srec;
     P.lrow = c->d_lrow;
     P.lrow32 = c->d_lrow32;
@@ -576,8 +575,7 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         setup_params(c.get());
         if (c->d_la)
             for (int n = 0; n <= N; ++n)
-                HQ_HIP(hqk::launch_lookahead(c->P64, c->layers[n], c->d_la, c->d_la + S, (uint32_t)c->nodes.size(),
-                                             s));
+                HQ_HIP(hqk::launch_lookahead(c->P64, c->layers[n], c->d_la, (uint32_t)c->nodes.size(), s));
         for (int n = 1; n <= N - 1; ++n)
             if (c->layers[n].stored)
                 HQ_HIP(hqk::launch_coef(c->P64, c->layers[n], c->d_coefs, (uint32_t)c->nodes.size(), s));

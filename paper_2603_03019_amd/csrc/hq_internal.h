@@ -70,8 +70,8 @@ struct SweepParams {
     const uint2* seg_prog;       // per seg_desc entry: (first program term, term count) of its tile
     const TrieNode* nodes;
     const double* coefs;         // stored coefficients of the top layers (unit-major per layer)
-    const double* la_w;          // look-ahead closed form: w(l) per state (layout order), or null
-    const double* la_z;          //   and z(l)
+    const double* la;            // look-ahead closed form: (w(l), z(l)) per state, interleaved
+                                 // (layout order), or null
     const double* scale;         // [N+1] storage scale of each layer (x = scale * p)
     const double* inv_scale;     // [N+1]
     DevScalars sc;

@@ -487,9 +487,9 @@ __device__ __forceinline__ void segment_compute(const SweepParams& P, const Laye
                 const double ps = (double)stored * is_self;
                 acc0 += ps;
                 acc1 += mu_m * ps;
-                if (P.la_w) {
-                    acc4 += ps * P.la_w[o];
-                    acc5 += ps * P.la_z[o];
+                if (P.la) {
+                    acc4 += ps * P.la[2 * (size_t)o];
+                    acc5 += ps * P.la[2 * (size_t)o + 1];
                 }
             }
         }
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
 // Layer scalars from the work-group partials of the kernel just run on the
 // same stream (one work-group, fixed summation order).
 // inner: 0 closed form, 1 one update, 2 literal loop with tolerance P.delta.
-// With the look-ahead closed form (P.la_w set): the write of layer n also
+// With the look-ahead closed form (P.la set): the write of layer n also
 // yields sum p_n w and sum p_n z, from which the closed-form alpha of layer
 // n + 1 follows before that layer is swept:
 //   alpha_{n+1} = beta_{n+1} S_muD(n+1) / (Lambda S_U(n+1)),
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode
         P.sc.mu[n] = mu;
         P.sc.alpha[n] = used;
         P.sc.delta[n] = tot[2];
-        if (P.la_w) {
+        if (P.la) {
             P.sc.wsum[n] = tot[4];
             P.sc.zsum[n] = tot[5];
             // the next layer of this iteration, or layer 1 of the next one
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(HQ_WG) void finalize_kernel(SweepParams P, int mode
         P.sc.mu[n] = tot[1];
         P.sc.alpha[n] = 0.0;
         P.sc.delta[n] = 0.0;
-        if (P.la_w) {
+        if (P.la) {
             P.sc.wsum[n] = tot[4];
             P.sc.zsum[n] = tot[5];
             if (n == N && N >= 2) lookahead_alpha(P, 1);  // every layer's sums are in
@@ -674,8 +674,8 @@ __global__ __launch_bounds__(HQ_WG) void coef_kernel(SweepParams P, LayerArgs A,
 // nodes whose first idle unit in l is u, eq. (3)).  r comes from the merged
 // preference trie: a node on a busy path whose own unit is idle passes its
 // whole rate to that unit.
-__global__ __launch_bounds__(HQ_WG) void lookahead_kernel(SweepParams P, LayerArgs A, double* __restrict__ w,
-                                                          double* __restrict__ z, uint32_t nnodes) {
+__global__ __launch_bounds__(HQ_WG) void lookahead_kernel(SweepParams P, LayerArgs A, double* __restrict__ wz,
+                                                          uint32_t nnodes) {
     const int tid = threadIdx.x;
     const int n = A.n, b = P.b, N = P.N;
     const uint32_t tiles = 1u << P.H;
@@ -703,8 +703,8 @@ __global__ __launch_bounds__(HQ_WG) void lookahead_kernel(SweepParams P, LayerAr
             }
             for (int u = 0; u < N; ++u)
                 if ((m >> u) & 1u) zv += P.nu[u] * (mu_m - P.nu[u]) / (P.Lam + mu_m - P.nu[u]);
-            w[off + t] = wv;
-            z[off + t] = zv;
+            wz[2 * (size_t)(off + t)] = wv;
+            wz[2 * (size_t)(off + t) + 1] = zv;
         }
     }
     (void)n;
@@ -763,9 +763,9 @@ __device__ __forceinline__ void init_segment(const SweepParams& P, const LayerAr
             if ((L >> l) & 1u) mu_lo += ro(P.nu)[l];
         acc0 += ps;
         acc1 += (mu_hi + mu_lo) * ps;
-        if (P.la_w) {
-            acc4 += ps * P.la_w[off + t];
-            acc5 += ps * P.la_z[off + t];
+        if (P.la) {
+            acc4 += ps * P.la[2 * (size_t)(off + t)];
+            acc5 += ps * P.la[2 * (size_t)(off + t) + 1];
         }
     }
 }
@@ -1397,9 +1397,9 @@ hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams
     return hipGetLastError();
 }
 
-hipError_t launch_lookahead(const SweepParams& P, const LayerArgs& A, double* w, double* z, uint32_t nnodes,
+hipError_t launch_lookahead(const SweepParams& P, const LayerArgs& A, double* wz, uint32_t nnodes,
                             hipStream_t s) {
-    hipLaunchKernelGGL(lookahead_kernel, dim3(grid_for(A.groups)), dim3(HQ_WG), 0, s, P, A, w, z, nnodes);
+    hipLaunchKernelGGL(lookahead_kernel, dim3(grid_for(A.groups)), dim3(HQ_WG), 0, s, P, A, wz, nnodes);
     return hipGetLastError();
 }
 

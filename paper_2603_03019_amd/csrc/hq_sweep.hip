@@ -53,6 +53,7 @@ __device__ __forceinline__ const HQ_CONST T* cro(const T* p) {
 constexpr int B = HQ_SWEEP_B;  // low bits per tile
 constexpr int WAVES = HQ_WG / 64;
 constexpr int RSRC_W3 = 0x00020000;  // buffer resource word 3 on gfx9 (32-bit data format, raw)
+constexpr int HQ_AUX_NT = 2;         // cache-policy operand of a buffer load: non-temporal
 
 // S_WRITE_LA: the sweep of the closed inner form, which also accumulates
 // the look-ahead sums of the next layers' alpha
@@ -91,6 +92,7 @@ __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff,
         return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, T v, uint32_t voff, uint32_t soff) {
     if constexpr (sizeof(T) == 8)
@@ -179,7 +181,7 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
                                         const double tcv, const uint32_t pov, const uint32_t tmk, const double trt,
                                         const Scal& s, double* wlds, T* stage, const uint16_t* s_rank,
                                         double& acc0, double& acc1, double& acc2, double& acc3, double& acc4,
-                                        double& acc5, const double* la_w, const double* la_z) {
+                                        double& acc5, __amdgpu_buffer_rsrc_t lar, const uint32_t lbase) {
     constexpr uint32_t SZ = sizeof(T);
     const int lane = threadIdx.x & 63;
     const uint32_t desc = rl(rec, HQ_REC_DESC);
@@ -230,6 +232,7 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
     } else if (lane < P.N) {
         wlds[32 + lane - B] = wA;
     }
+    const uint32_t la_o = (rl(rec, HQ_REC_SELF) - lbase) * 16u;
     for (uint32_t i = lane; i < cnt_dn; i += 64) stage[i] = (T)bload<T>(xr, i * SZ, o_dn);
     for (uint32_t i = lane; i < cnt_up; i += 64) stage[cnt_dn + i] = (T)bload<T>(xr, i * SZ, o_up);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -252,12 +255,15 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
 #pragma unroll
         for (int k = 0; k < HF; ++k) vh[k] = bload<T>(xr, t8, o_hi[k]);
         const double vt0 = bload<T>(xr, t8, o_t0), vt1 = bload<T>(xr, t8, o_t1);
-        // look-ahead weights of this state (closed form), in flight with the rest
+        // closed form: the look-ahead pair (w, z) of this state, one 16-byte
+        // load in flight with the neighbours; the pairs are read once per
+        // sweep, so the load is marked non-temporal (they should not push
+        // neighbour values out of the L2)
         double lw = 0.0, lz = 0.0;
         if (MODE == S_WRITE_LA) {
-            const uint32_t o64 = rl(rec, HQ_REC_SELF) + t;
-            lw = la_w[o64];
-            lz = la_z[o64];
+            const u32x4 wz = __builtin_amdgcn_raw_buffer_load_b128(lar, la_o + t * 16u, 0, HQ_AUX_NT);
+            lw = __builtin_bit_cast(double, (unsigned long long)wz[0] | ((unsigned long long)wz[1] << 32));
+            lz = __builtin_bit_cast(double, (unsigned long long)wz[2] | ((unsigned long long)wz[3] << 32));
         }
 #pragma unroll
         for (int i = 0; i < B; ++i) {
@@ -369,8 +375,10 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(MODE == S
     const __amdgpu_buffer_rsrc_t rowr = __builtin_amdgcn_make_buffer_rsrc(const_cast<LowRow*>(rows), 0,
                                                                           (1 << B) * (int)sizeof(LowRow), RSRC_W3);
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0, acc5 = 0.0;
-    const double* la_w = MODE == S_WRITE_LA ? P.la_w : nullptr;
-    const double* la_z = MODE == S_WRITE_LA ? P.la_z : nullptr;
+    // look-ahead pairs (w, z) of layer n, 16 bytes per state
+    const uint32_t lbase = cro(P.layer_off)[n];
+    const __amdgpu_buffer_rsrc_t lar = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(MODE == S_WRITE_LA ? P.la + 2 * (size_t)lbase : P.partials), 0, -1, RSRC_W3);
     // wave-granular segments; the eight XCDs sweep contiguous eighths
     const uint32_t G = gridDim.x, wg = blockIdx.x;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -421,7 +429,7 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(MODE == S
         const uint32_t rec2 = load_rec(si + 2 * step);
         const Tile t1 = load_tile(si + step, rec1);
         segment<T, MODE, TRACK, HF>(P, xr, rowr, base, rec0, t0.tcv, t0.pov, t0.tmk, t0.trt, s, wlds, stage, s_rank,
-                                    acc0, acc1, acc2, acc3, acc4, acc5, la_w, la_z);
+                                    acc0, acc1, acc2, acc3, acc4, acc5, lar, lbase);
         rec0 = rec1;
         rec1 = rec2;
         t0 = t1;
@@ -504,7 +512,7 @@ static uint32_t launch_one(const SweepParams& P, const LayerArgs& A, T* x, int i
 template <typename T, int HF>
 static uint32_t launch_h(int mode, bool track, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
                          hipStream_t s) {
-    if (mode == 1 /* M_WRITE */ && P.la_w) return track ? 0u : launch_one<T, S_WRITE_LA, false, HF>(P, A, x, inner_one, s);
+    if (mode == 1 /* M_WRITE */ && P.la) return track ? 0u : launch_one<T, S_WRITE_LA, false, HF>(P, A, x, inner_one, s);
     if (mode == 1 && !track) return launch_one<T, S_WRITE, false, HF>(P, A, x, inner_one, s);
     if (mode == 1) return launch_one<T, S_WRITE, true, HF>(P, A, x, inner_one, s);
     if (mode == 0 /* M_PASS1 */ && track) return launch_one<T, S_PASS1, true, HF>(P, A, x, inner_one, s);
