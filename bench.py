@@ -49,7 +49,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(N: int, precision: str):
     """HBM bytes per outer iteration of the layer kernels, from the committed
     counter summary; None when the sweep's sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"layer_kernel_n{N}_{precision}_hbm_bytes.txt")
+    path = os.path.join(ROOT, "profiles", f"sweep_n{N}_{precision}_hbm_bytes.txt")
     if not os.path.exists(path):
         return None
     fields = {}

@@ -296,9 +296,11 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
                 A = fma(wlds[32 + k], vh[k], A);
         }
         // per-tile program terms: a busy unit u gains `rate` in the states
-        // whose low bits contain the term's mask; the unit's neighbour value
-        // is read again (a high unit's from memory, where it was just read; a
-        // low unit's, only where it is busy, from the staging area)
+        // whose low bits contain the term's mask.  The unit's terms are summed
+        // first, then multiplied once by its neighbour value: a high unit's
+        // from registers (the second copy of the first two such units, a
+        // select over the loaded set for the others), a low unit's read
+        // again from the staging area and kept only where the unit is busy.
         const uint32_t nL = ~L;
         uint32_t um = pmask;
         while (um) {
