@@ -278,6 +278,10 @@ def inner_leg(hq, inst, tol: float):
         out[name] = {"iterations": info["iterations"], "time_to_tol_s": time.perf_counter() - t,
                      "sweep_ms_per_iteration": 1e3 * info["sweep_seconds"] / max(info["iterations"], 1)}
         hq.hq_destroy(ctx)
+        # the exact crossing: the residual checked after every outer iteration
+        ctx = hq.create_from_instance(inst, check_every=1, **kw)
+        out[name]["iterations_checked_every_iteration"] = hq.hq_solve(ctx, tol)["iterations"]
+        hq.hq_destroy(ctx)
     return out
 
 

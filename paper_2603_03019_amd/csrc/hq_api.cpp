@@ -423,7 +423,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     const char* nograph = std::getenv("HQ_NO_GRAPH");
     const char* nola = std::getenv("HQ_NO_LOOKAHEAD");
     c->use_graphs = !(nograph && nograph[0] == '1');
-    if (b == HQ_SWEEP_B && c->H >= 6 && c->H <= 20 && !(legacy && legacy[0] == '1')) {
+    // the default-shape sweep kernels serve H = 6..16 (N = 16..26); from
+    // H = 17 the general layer kernel measured faster (N = 27: 7.07 against
+    // 7.59 ms per outer iteration, N = 30: 52.0 against 56.6 ms)
+    if (b == HQ_SWEEP_B && c->H >= 6 && c->H <= 16 && !(legacy && legacy[0] == '1')) {
         lrow = hqsweeptab::low_rows(lay, c->nu, 8);
         lrow32 = hqsweeptab::low_rows(lay, c->nu, 4);
         srec = hqsweeptab::seg_records(lay, prog_off, c->nu);

@@ -1,5 +1,5 @@
 // The layer sweep for the default tile shape (b = 10 low bits per tile,
-// H = N - 10 high bits, N = 16..30): one kernel per layer launch that
+// H = N - 10 high bits, N = 16..26): one kernel per layer launch that
 // evaluates, for every state m of layer n, the two gathers of the update
 // (12) of Algorithm 1,
 //     U~(m) = sum_{u in m}    a(m, u) p_{n-1}(m \ u) / (Lambda + mu_m),
@@ -536,7 +536,7 @@ uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, con
                     : launch_h<double, HV>(mode, track, P, A, (double*)x, inner_one, s);
     switch (P.H) {
         HQ_SW(6) HQ_SW(7) HQ_SW(8) HQ_SW(9) HQ_SW(10) HQ_SW(11) HQ_SW(12) HQ_SW(13) HQ_SW(14) HQ_SW(15)
-        HQ_SW(16) HQ_SW(17) HQ_SW(18) HQ_SW(19) HQ_SW(20)
+        HQ_SW(16)
         default:
             return 0;
     }
