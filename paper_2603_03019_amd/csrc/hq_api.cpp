@@ -29,6 +29,8 @@
 namespace hqk {
 hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
                         int inner_one, hipStream_t s);
+hipError_t launch_write_chain(bool track_delta, bool fp32, const SweepParams& P, const LayerArgs* layers, int N,
+                              void* x, int inner_one, double* half0, double* half1, bool fuse, hipStream_t s);
 hipError_t launch_init(bool fp32, const SweepParams& P, const LayerArgs& A, void* x, const double* xu,
                        const double* given, const uint32_t* orig_bit, hipStream_t s);
 hipError_t launch_scalars(const SweepParams& P, int want_residual, hipStream_t s);
@@ -51,6 +53,9 @@ hipError_t noalloc_scratch(int device, BatchScratch** out);
 
 // automatic choice of stored-coefficient layers (see hq_create)
 #define HQ_STORE_TERMS 32.0
+// layers of at least this many program terms per state go to the general
+// layer kernel rather than the default-shape sweep
+#define HQ_GENERAL_TERMS 10.0
 #define HQ_STORE_BYTES (16ull << 30)
 
 namespace {
@@ -147,7 +152,8 @@ struct hq_ctx {
     LowRow* d_lrow = nullptr;    // its low-pattern rows (FP64 offsets)
     LowRow* d_lrow32 = nullptr;  // and with FP32 offsets
     SweepParams P64{}, P32{};
-    bool use_graphs = true;            // replay captured iterations (HQ_NO_GRAPH=1: launch eagerly)
+    bool use_graphs = true;  // replay captured iterations (HQ_NO_GRAPH=1: launch eagerly)
+    bool fuse = true;        // small layers form the previous layer's scalars (HQ_NO_FUSE=1: never)
     hipGraphExec_t iter_exec[2][2] = {};  // [FP32 storage][delta tracking]
     bool have_iterate = false;
     bool learned = false;      // product-form weights came from the network
@@ -423,6 +429,9 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     const char* nograph = std::getenv("HQ_NO_GRAPH");
     const char* nola = std::getenv("HQ_NO_LOOKAHEAD");
     c->use_graphs = !(nograph && nograph[0] == '1');
+    // HQ_NO_FUSE=1: a finalize launch after every layer (for comparisons)
+    const char* nofuse = std::getenv("HQ_NO_FUSE");
+    c->fuse = !(nofuse && nofuse[0] == '1');
     // the default-shape sweep kernels serve H = 6..16 (N = 16..26); from
     // H = 17 the general layer kernel measured faster (N = 27: 7.07 against
     // 7.59 ms per outer iteration, N = 30: 52.0 against 56.6 ms)
@@ -451,9 +460,10 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     // device's free memory.  Reading N stored values per state costs about
     // as much as evaluating ~30 program terms; below ~20 terms storing is
     // measurably slower.
-    int top = o.stored_layers;
-    if (top == 0) {
-        std::vector<double> num(N + 1, 0.0), den(N + 1, 0.0);
+    // program terms per state of each layer (tile program lengths weighted
+    // by the tiles' states in the layer)
+    std::vector<double> num(N + 1, 0.0), den(N + 1, 0.0);
+    {
         const uint64_t ntiles = 1ull << (N - b);
         for (uint64_t T = 0; T < ntiles; ++T) {
             const double len = (double)(prog_off[T * (N + 1) + N] - prog_off[T * (N + 1)]);
@@ -464,6 +474,9 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
                 den[h + q] += w;
             }
         }
+    }
+    int top = o.stored_layers;
+    if (top == 0) {
         uint64_t budget = HQ_STORE_BYTES;
         size_t free_b = 0, total_b = 0;
         if ((o.device < 0 || hipSetDevice(o.device) == hipSuccess) && hipMemGetInfo(&free_b, &total_b) == hipSuccess)
@@ -488,6 +501,12 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
             c->layers[n].stored = 1;
             c->layers[n].coef_base = coef_total;
             coef_total += (unsigned long long)N * c->layers[n].count;
+        } else if (num[n] >= HQ_GENERAL_TERMS * den[n]) {
+            // long programs: the general kernel, which forms each busy unit's
+            // coefficient next to its neighbour value, measured faster there
+            // (N = 26 clustered, layers 16..19: 252, 213, 163, 133 against
+            // 259, 228, 174, 144 us)
+            c->layers[n].general = 1;
         }
     }
     // storage scales: 1 for FP64; for FP32 the power of two nearest C(N, n)
@@ -518,6 +537,9 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->d_mu_lo = dalloc<double>(lo);
         c->d_tcoef = dalloc<double>(tcoef.size());
         c->d_scal = dalloc<double>(10 * (N + 1) + 8);
+        // two halves of max_groups partials each (consecutive layer launches of an
+        // outer iteration alternate between them; a launch writes at most one
+        // partial per segment of its layer)
         c->d_part = dalloc<double>(max_groups * 32);
         c->d_scale64 = dalloc<double>(s64.size());
         c->d_scale32 = dalloc<double>(s32.size());
@@ -629,10 +651,17 @@ void run_init(hq_ctx* c, bool fp32) {
 
 // The launches of one outer iteration: for n = 1..N-1 in order, the layer
 // kernel (and for the closed and literal inner forms its first pass) with
-// the finalize launch that forms the layer's scalars.
+// the finalize launch that forms the layer's scalars.  With one update or
+// the look-ahead closed form each layer launch forms the previous layer's
+// scalars itself, and only the last layer has a finalize launch.
 void launch_iteration(hq_ctx* c, bool track_delta) {
     const bool fp32 = c->active_fp32;
     const int inner = c->opts.inner;  // 0 closed, 1 one update, 2 literal loop
+    if (inner == HQ_INNER_ONE || (inner == HQ_INNER_CLOSED && c->d_la)) {
+        HQ_HIP(hqk::launch_write_chain(track_delta, fp32, c->params(fp32), c->layers.data(), c->N, c->xbuf(fp32),
+                                       inner, c->d_part, c->d_part + c->max_groups * HQ_NPART, c->fuse, c->stream));
+        return;
+    }
     for (int n = 1; n <= c->N - 1; ++n) {
         const LayerArgs& A = c->layers[n];
         // the closed form's first pass is not needed when its sums come from

@@ -89,6 +89,7 @@ struct LayerArgs {
     uint32_t desc_base;    // first entry of this layer in seg_desc
     uint32_t count;        // C(N, n)
     int stored;            // coefficients of this layer are stored in coefs
+    int general;           // swept by the general layer kernel (long tile programs)
     unsigned long long coef_base;  // offset of this layer in coefs (unit-major, count per unit)
     double e_n;            // product-form normaliser for init
     int init_mode;

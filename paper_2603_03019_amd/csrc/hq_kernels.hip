@@ -25,6 +25,7 @@
 // Each kernel ends with a deterministic two-level FP64 reduction: wave
 // shuffles, one partial per work-group, and a fixed-order sum by the last
 // work-group to finish, which also derives the layer scalars.
+#include "hq_fuse.h"
 #include "hq_internal.h"
 #include "hq_layout.h"
 #include "hq_schedule.h"
@@ -509,9 +510,13 @@ __device__ __forceinline__ void segment_update(const SweepParams& P, const Layer
                                                   unused, unused4, unused5);
 }
 
+// Occupancy floors (waves per SIMD) that the register allocation must keep:
+// 4 with computed coefficients, 3 with stored ones from H = 14 (the counts
+// the kernel reaches without the fused prologue of hq_fuse.h).
 template <typename T, int MODE, bool TRACK_DELTA, bool STORED, int BF = 0, int HF = 0>
-__global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
-                                                      int inner_one) {
+__global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(STORED ? (HF >= 14 ? 3 : 2) : 4, 8))) void
+layer_kernel(SweepParams P, LayerArgs A, T* __restrict__ x, int inner_one, hqfuse::FuseArgs F) {
+    __shared__ double s_fred[HQ_NPART][HQ_WG / 64];
     __shared__ uint16_t s_rank[1 << HQ_MAXB];    // colex rank of a low pattern inside its class
     __shared__ uint16_t s_unrank[1 << HQ_MAXB];  // low patterns by (popcount, value)
     __shared__ uint32_t s_qstart[HQ_MAXB + 2];
@@ -524,7 +529,15 @@ __global__ __launch_bounds__(HQ_WG) void layer_kernel(SweepParams P, LayerArgs A
     }
     if (tid <= b + 1) s_qstart[tid] = P.lo_qstart[tid];
     __syncthreads();
-    const ModeScalars ms = mode_scalars<MODE>(P, A.n, inner_one, P.sc.lam, P.sc.mu, P.sc.alpha, P.sc.pn);
+    // the previous layer's scalars, when its finalize launch is fused into this one
+    hqfuse::Prev pv{0.0, 0.0};
+    const bool fused = MODE == M_WRITE && F.prev != nullptr;
+    if (fused) pv = hqfuse::prologue<HQ_WG>(P, A.n, inner_one, F, s_fred);
+    ModeScalars ms = mode_scalars<MODE>(P, A.n, inner_one, P.sc.lam, P.sc.mu, P.sc.alpha, P.sc.pn);
+    if (fused) {
+        ms.alpha0 = P.sc.mu[A.n] / pv.lam_prev;
+        ms.alpha = inner_one == 1 ? ms.alpha0 : (P.la ? pv.alpha_la : ms.alpha);
+    }
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0, acc5 = 0.0;
     // Software pipeline over this wave's segments: the scalar record of
     // segment i+2 and the lane-parallel record of segment i+1 are in flight
@@ -1320,18 +1333,18 @@ static uint32_t grid_for(uint32_t groups) {
 // run-time-shaped kernels.
 template <typename T, int BF, int HF>
 static void launch_fixed(int mode, bool stored, bool track, const SweepParams& P, const LayerArgs& A, T* x,
-                         int inner_one, hipStream_t s) {
+                         int inner_one, const hqfuse::FuseArgs& F, hipStream_t s) {
     dim3 grid(grid_for(A.groups)), block(HQ_WG);
     if (mode == M_WRITE && stored)
-        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, true, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, true, BF, HF>), grid, block, 0, s, P, A, x, inner_one, F);
     else if (mode == M_WRITE)
-        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one, F);
     else if (mode == M_PASS1 && track)
-        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, true, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, true, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one, F);
     else if (mode == M_PASS1)
-        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one, F);
     else
-        hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, false, BF, HF>), grid, block, 0, s, P, A, x, inner_one, F);
 }
 
 // The sweep (computed or stored coefficients, without the delta tracking of
@@ -1339,13 +1352,13 @@ static void launch_fixed(int mode, bool stored, bool track, const SweepParams& P
 // forms and the residual, for computed coefficients.
 template <typename T>
 static bool launch_layer_fixed(int mode, bool stored, bool track, const SweepParams& P, const LayerArgs& A,
-                               T* x, int inner_one, hipStream_t s) {
+                               T* x, int inner_one, const hqfuse::FuseArgs& F, hipStream_t s) {
     if (mode == M_WRITE && track) return false;
     if (mode != M_WRITE && stored) return false;
-#define HQ_FIXED(BV, HV)                                                   \
-    if (P.b == BV && P.H == HV) {                                          \
-        launch_fixed<T, BV, HV>(mode, stored, track, P, A, x, inner_one, s); \
-        return true;                                                       \
+#define HQ_FIXED(BV, HV)                                                      \
+    if (P.b == BV && P.H == HV) {                                             \
+        launch_fixed<T, BV, HV>(mode, stored, track, P, A, x, inner_one, F, s); \
+        return true;                                                          \
     }
     HQ_FIXED(10, 6) HQ_FIXED(10, 7) HQ_FIXED(10, 8) HQ_FIXED(10, 9) HQ_FIXED(10, 10) HQ_FIXED(10, 11)
     HQ_FIXED(10, 12) HQ_FIXED(10, 13) HQ_FIXED(10, 14) HQ_FIXED(10, 15) HQ_FIXED(10, 16) HQ_FIXED(10, 17)
@@ -1356,44 +1369,73 @@ static bool launch_layer_fixed(int mode, bool stored, bool track, const SweepPar
 
 template <typename T, bool STORED>
 static void launch_layer_s(int mode, bool track_delta, const SweepParams& P, const LayerArgs& A, T* x,
-                           int inner_one, hipStream_t s) {
+                           int inner_one, const hqfuse::FuseArgs& F, hipStream_t s) {
     dim3 grid(grid_for(A.groups)), block(HQ_WG);
-    if (launch_layer_fixed<T>(mode, STORED, track_delta, P, A, x, inner_one, s)) return;
+    if (launch_layer_fixed<T>(mode, STORED, track_delta, P, A, x, inner_one, F, s)) return;
     if (mode == M_PASS1 && track_delta)
-        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, true, STORED>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, true, STORED>), grid, block, 0, s, P, A, x, inner_one, F);
     else if (mode == M_PASS1)
-        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_PASS1, false, STORED>), grid, block, 0, s, P, A, x, inner_one, F);
     else if (mode == M_WRITE && track_delta)
-        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, true, STORED>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, true, STORED>), grid, block, 0, s, P, A, x, inner_one, F);
     else if (mode == M_WRITE)
-        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_WRITE, false, STORED>), grid, block, 0, s, P, A, x, inner_one, F);
     else
-        hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, STORED>), grid, block, 0, s, P, A, x, inner_one);
+        hipLaunchKernelGGL((layer_kernel<T, M_RESID, false, STORED>), grid, block, 0, s, P, A, x, inner_one, F);
 }
 
 uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
-                      int inner_one, hipStream_t s);
+                      int inner_one, const hqfuse::FuseArgs& F, hipStream_t s);
+
+// One layer launch without its finalize; returns the number of work-group
+// partials it writes (at P.partials).
+static uint32_t launch_layer_only(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A,
+                                  void* x, int inner_one, const hqfuse::FuseArgs& F, hipStream_t s) {
+    // the default tile shape runs on the sweep kernels of hq_sweep.hip
+    const uint32_t parts = launch_sweep(mode, track_delta, fp32, P, A, x, inner_one, F, s);
+    if (parts) return parts;
+    if (fp32) {
+        if (A.stored)
+            launch_layer_s<float, true>(mode, track_delta, P, A, (float*)x, inner_one, F, s);
+        else
+            launch_layer_s<float, false>(mode, track_delta, P, A, (float*)x, inner_one, F, s);
+    } else {
+        if (A.stored)
+            launch_layer_s<double, true>(mode, track_delta, P, A, (double*)x, inner_one, F, s);
+        else
+            launch_layer_s<double, false>(mode, track_delta, P, A, (double*)x, inner_one, F, s);
+    }
+    return grid_for(A.groups);
+}
 
 hipError_t launch_layer(int mode, bool track_delta, bool fp32, const SweepParams& P, const LayerArgs& A,
                         void* x, int inner_one, hipStream_t s) {
-    // the default tile shape runs on the sweep kernels of hq_sweep.hip
-    const uint32_t parts = launch_sweep(mode, track_delta, fp32, P, A, x, inner_one, s);
-    if (parts) {
-        hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(HQ_WG), 0, s, P, mode, A.n, parts, inner_one);
-        return hipGetLastError();
+    const hqfuse::FuseArgs none{nullptr, 0u};
+    const uint32_t parts = launch_layer_only(mode, track_delta, fp32, P, A, x, inner_one, none, s);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(HQ_WG), 0, s, P, mode, A.n, parts, inner_one);
+    return hipGetLastError();
+}
+
+// The sweeps of layers 1..N-1 of one outer iteration (one update, or the
+// look-ahead closed form).  A layer launch forms the previous layer's
+// scalars itself (hq_fuse.h) when that layer wrote at most HQ_FUSE_PARTS
+// partials; after a larger layer, where every work-group reading all the
+// partials would cost more than the one-work-group launch, the finalize
+// launch stays.  Layer n writes its partials to half[n & 1].
+#define HQ_FUSE_PARTS 1024
+hipError_t launch_write_chain(bool track_delta, bool fp32, const SweepParams& P, const LayerArgs* layers, int N,
+                              void* x, int inner_one, double* half0, double* half1, bool fuse, hipStream_t s) {
+    hqfuse::FuseArgs F{nullptr, 0u};
+    SweepParams Pn = P;
+    for (int n = 1; n <= N - 1; ++n) {
+        Pn.partials = (n & 1) ? half1 : half0;
+        const uint32_t parts = launch_layer_only(M_WRITE, track_delta, fp32, Pn, layers[n], x, inner_one, F, s);
+        F = hqfuse::FuseArgs{Pn.partials, parts};
+        if (!fuse || parts > HQ_FUSE_PARTS || n == N - 1) {
+            hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(HQ_WG), 0, s, Pn, (int)M_WRITE, n, parts, inner_one);
+            F = hqfuse::FuseArgs{nullptr, 0u};
+        }
     }
-    if (fp32) {
-        if (A.stored)
-            launch_layer_s<float, true>(mode, track_delta, P, A, (float*)x, inner_one, s);
-        else
-            launch_layer_s<float, false>(mode, track_delta, P, A, (float*)x, inner_one, s);
-    } else {
-        if (A.stored)
-            launch_layer_s<double, true>(mode, track_delta, P, A, (double*)x, inner_one, s);
-        else
-            launch_layer_s<double, false>(mode, track_delta, P, A, (double*)x, inner_one, s);
-    }
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(HQ_WG), 0, s, P, mode, A.n, grid_for(A.groups), inner_one);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@
 //
 // Arithmetic is FP64 throughout; with FP32 storage the neighbour values are
 // widened on load and the written value rounded once.
+#include "hq_fuse.h"
 #include "hq_internal.h"
 
 #include <math.h>
@@ -110,8 +111,11 @@ struct Scal {
     double is_self, pself;    // inverse storage scale of layer n; p(n) (residual)
 };
 
+// fused: lambda^k(n-1) (and with the look-ahead alpha_n) come from the
+// launch's own reduction of the previous layer's partials (hq_fuse.h)
 template <int MODE>
-__device__ __forceinline__ Scal load_scal(const SweepParams& P, int n, int inner_one) {
+__device__ __forceinline__ Scal load_scal(const SweepParams& P, int n, int inner_one, bool fused,
+                                          const hqfuse::Prev& pv) {
     Scal s{};
     const int N = P.N;
     const double is_dn = P.inv_scale[n - 1], is_up = P.inv_scale[n + 1];
@@ -122,11 +126,12 @@ __device__ __forceinline__ Scal load_scal(const SweepParams& P, int n, int inner
         s.pself = P.sc.pn[n];
     } else {
         const double beta = P.sc.lam[n] / P.sc.mu[n + 1];    // lambda^{k-1}(n) / mu^{k-1}(n+1)
-        const double alpha0 = P.sc.mu[n] / P.sc.lam[n - 1];  // mu^{k-1}(n) / lambda^k(n-1)
+        const double lam_prev = fused ? pv.lam_prev : P.sc.lam[n - 1];
+        const double alpha0 = P.sc.mu[n] / lam_prev;  // mu^{k-1}(n) / lambda^k(n-1)
         s.alpha0 = alpha0;
         s.beta0 = beta;
         if (MODE == S_WRITE || MODE == S_WRITE_LA) {
-            const double alpha = inner_one == 1 ? alpha0 : P.sc.alpha[n];
+            const double alpha = inner_one == 1 ? alpha0 : (fused && P.la ? pv.alpha_la : P.sc.alpha[n]);
             const double s_self = P.scale[n];
             s.wa = alpha * is_dn * s_self;
             s.wb = beta * is_up * s_self;
@@ -360,7 +365,7 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
 
 template <typename T, int MODE, bool TRACK, int HF>
 __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(MODE == S_PASS1 ? 4 : 5, 8))) void sweep_kernel(SweepParams P, LayerArgs A, T* __restrict__ x,
-                                                      int inner_one) {
+                                                      int inner_one, hqfuse::FuseArgs F) {
     __shared__ double s_w[WAVES * 64];
     __shared__ T s_stage[WAVES][HQ_SWEEP_STAGE];  // per wave: segments (T, q - 1) and (T, q + 1)
     __shared__ uint16_t s_rank[1 << B];
@@ -369,7 +374,11 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(MODE == S
     for (int i = tid; i < (1 << B); i += HQ_WG) s_rank[i] = P.lo_rank[i];
     __syncthreads();
     const int n = A.n;
-    const Scal s = load_scal<MODE>(P, n, inner_one);
+    // the previous layer's scalars, when its finalize launch is fused into this one
+    const bool fused = (MODE == S_WRITE || MODE == S_WRITE_LA) && F.prev != nullptr;
+    hqfuse::Prev pv{0.0, 0.0};
+    if (fused) pv = hqfuse::prologue<HQ_WG>(P, n, inner_one, F, s_red);
+    const Scal s = load_scal<MODE>(P, n, inner_one, fused, pv);
     // the window of layers n - 1 .. n + 1 (offsets fit 32 bits up to N = 30)
     const uint32_t base = cro(P.layer_off)[n - 1];
     const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(x + base, 0, -1, RSRC_W3);
@@ -505,35 +514,40 @@ static uint32_t sweep_grid(uint32_t groups) {
 }
 
 template <typename T, int MODE, bool TRACK, int HF>
-static uint32_t launch_one(const SweepParams& P, const LayerArgs& A, T* x, int inner_one, hipStream_t s) {
+static uint32_t launch_one(const SweepParams& P, const LayerArgs& A, T* x, int inner_one, const hqfuse::FuseArgs& F,
+                           hipStream_t s) {
     const uint32_t g = sweep_grid<T, MODE, TRACK, HF>(A.groups);
-    hipLaunchKernelGGL((sweep_kernel<T, MODE, TRACK, HF>), dim3(g), dim3(HQ_WG), 0, s, P, A, x, inner_one);
+    hipLaunchKernelGGL((sweep_kernel<T, MODE, TRACK, HF>), dim3(g), dim3(HQ_WG), 0, s, P, A, x, inner_one, F);
     return g;
 }
 
 template <typename T, int HF>
 static uint32_t launch_h(int mode, bool track, const SweepParams& P, const LayerArgs& A, T* x, int inner_one,
-                         hipStream_t s) {
-    if (mode == 1 /* M_WRITE */ && P.la) return track ? 0u : launch_one<T, S_WRITE_LA, false, HF>(P, A, x, inner_one, s);
-    if (mode == 1 && !track) return launch_one<T, S_WRITE, false, HF>(P, A, x, inner_one, s);
-    if (mode == 1) return launch_one<T, S_WRITE, true, HF>(P, A, x, inner_one, s);
-    if (mode == 0 /* M_PASS1 */ && track) return launch_one<T, S_PASS1, true, HF>(P, A, x, inner_one, s);
-    if (mode == 0) return launch_one<T, S_PASS1, false, HF>(P, A, x, inner_one, s);
-    return launch_one<T, S_RESID, false, HF>(P, A, x, inner_one, s);
+                         const hqfuse::FuseArgs& F, hipStream_t s) {
+    if (mode == 1 /* M_WRITE */ && P.la)
+        return track ? 0u : launch_one<T, S_WRITE_LA, false, HF>(P, A, x, inner_one, F, s);
+    if (mode == 1 && !track) return launch_one<T, S_WRITE, false, HF>(P, A, x, inner_one, F, s);
+    if (mode == 1) return launch_one<T, S_WRITE, true, HF>(P, A, x, inner_one, F, s);
+    const hqfuse::FuseArgs none{nullptr, 0u};
+    if (mode == 0 /* M_PASS1 */ && track) return launch_one<T, S_PASS1, true, HF>(P, A, x, inner_one, none, s);
+    if (mode == 0) return launch_one<T, S_PASS1, false, HF>(P, A, x, inner_one, none, s);
+    return launch_one<T, S_RESID, false, HF>(P, A, x, inner_one, none, s);
 }
 
 // Launch the sweep kernel of layer A.n for the default tile shape; returns
 // the number of work-groups (whose partials the finalize launch reads), or
-// 0 when this shape or layer is not covered (stored coefficients, another
-// tile width, the end layers of the residual, the closed form's sweep with
-// the paper's delta tracking).
+// 0 when this shape or layer is not covered (stored coefficients, long
+// tile programs, another tile width, the end layers of the residual, the
+// closed form's sweep with the paper's delta tracking).
 uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
-                      int inner_one, hipStream_t s) {
-    if (P.b != B || A.stored || !P.srec || !P.lrow || A.n < 1 || A.n >= P.N) return 0;
+                      int inner_one, const hqfuse::FuseArgs& F, hipStream_t s) {
+    // (the closed form's look-ahead sweep keeps its long-program layers: the
+    // general kernel reads the look-ahead weights after its neighbours)
+    if (P.b != B || A.stored || (A.general && !P.la) || !P.srec || !P.lrow || A.n < 1 || A.n >= P.N) return 0;
 #define HQ_SW(HV)                                                                     \
     case HV:                                                                          \
-        return fp32 ? launch_h<float, HV>(mode, track, P, A, (float*)x, inner_one, s) \
-                    : launch_h<double, HV>(mode, track, P, A, (double*)x, inner_one, s);
+        return fp32 ? launch_h<float, HV>(mode, track, P, A, (float*)x, inner_one, F, s) \
+                    : launch_h<double, HV>(mode, track, P, A, (double*)x, inner_one, F, s);
     switch (P.H) {
         HQ_SW(6) HQ_SW(7) HQ_SW(8) HQ_SW(9) HQ_SW(10) HQ_SW(11) HQ_SW(12) HQ_SW(13) HQ_SW(14) HQ_SW(15)
         HQ_SW(16)

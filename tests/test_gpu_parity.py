@@ -309,6 +309,39 @@ def test_graph_replays_match_eager_launches(inner, monkeypatch):
     hq.hq_destroy(e)
 
 
+@pytest.mark.parametrize("case", ["one-sweep", "closed-sweep", "one-stored", "delta-track"])
+def test_fused_layer_scalars_match_finalize_launches(case, monkeypatch):
+    """Small layers form the previous layer's scalars in their own launch
+    instead of a finalize launch after every layer: the iterate, the layer
+    scalars and a full solve are bitwise those of one finalize launch per
+    layer (sweep kernel and look-ahead sweep at N = 17, stored-coefficient
+    layers at N = 16, the paper's delta stopping rule)."""
+    if case == "one-stored":
+        inst, kw = config_instance(2, 5, N=16, J=150), dict(inner=hq.HQ_INNER_ONE, stored_layers=15)
+    elif case == "closed-sweep":
+        inst, kw = config_instance(3, 4, N=17, J=150), dict(inner=hq.HQ_INNER_CLOSED)
+    elif case == "delta-track":
+        inst, kw = config_instance(3, 4, N=17, J=150), dict(inner=hq.HQ_INNER_ONE, stop=hq.HQ_STOP_DELTA)
+    else:
+        inst, kw = config_instance(3, 4, N=17, J=150), dict(inner=hq.HQ_INNER_ONE)
+    say(f"case fused layer scalars {case}")
+    f = _gpu(inst, **kw)
+    monkeypatch.setenv("HQ_NO_FUSE", "1")
+    u = _gpu(inst, **kw)
+    monkeypatch.delenv("HQ_NO_FUSE")
+    for k in range(5):
+        hq.hq_iterate(f, 1)
+        hq.hq_iterate(u, 1)
+        assert np.array_equal(hq.hq_conditional(f), hq.hq_conditional(u)), f"iteration {k}"
+        assert np.array_equal(hq.hq_layer_scalars(f), hq.hq_layer_scalars(u)), f"iteration {k}"
+    tol = 1e-9 if case == "delta-track" else 1e-11
+    a, b = hq.hq_solve(f, tol), hq.hq_solve(u, tol)
+    assert a["iterations"] == b["iterations"]
+    assert np.array_equal(hq.hq_state(f), hq.hq_state(u))
+    hq.hq_destroy(f)
+    hq.hq_destroy(u)
+
+
 @pytest.mark.parametrize("stored", [-1, 4])
 def test_lookahead_closed_form_matches_two_passes_and_oracle(stored, monkeypatch):
     """The closed inner form in one pass per layer: the sums behind alpha_n
