@@ -37,7 +37,7 @@ extern "C" {
 typedef struct hq_ctx hq_ctx; /* opaque; owns its host and device memory */
 typedef struct hq_mlp hq_mlp; /* opaque; the warm-start network (see below) */
 
-#define HQ_MLP_IN 32      /* feature slots per unit (16 used, the rest zero) */
+#define HQ_MLP_IN 32      /* feature slots per unit (19 used, the rest zero) */
 #define HQ_MLP_HIDDEN 256 /* width of both hidden layers */
 #define HQ_MLP_PARAMS (HQ_MLP_IN * HQ_MLP_HIDDEN + HQ_MLP_HIDDEN + HQ_MLP_HIDDEN * HQ_MLP_HIDDEN + \
                        HQ_MLP_HIDDEN + HQ_MLP_HIDDEN + 1)
@@ -314,7 +314,10 @@ int hq_num_units(const hq_ctx* ctx);
  * arguments as hq_create): relative service rate, shares of demand that
  * rank the unit at positions 0..7 and 8+, offered load, load-discounted
  * exposure, N/32, rate relative to the fastest unit, first-choice share
- * times N, and a constant 1. */
+ * times N, a constant 1, and the independence approximation of the unit's
+ * utilisation (units busy independently; a call reaches a unit when every
+ * unit its node ranks earlier is busy): the approximate utilisation, the
+ * share of calls that reach the unit, and the clipped log-odds / 8. */
 hq_status hq_mlp_features(int N, int J, const double* lambda_j, const double* mu_i,
                           const int32_t* pref_lists, float* features);
 

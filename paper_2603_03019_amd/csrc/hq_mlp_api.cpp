@@ -165,6 +165,26 @@ void hq_mlp_features_impl(int N, int J, const double* lam, const double* mu, con
                 r *= load;
             }
         }
+    // The independence approximation of the loss system's utilisations (in
+    // the spirit of Larson's approximate hypercube): a call from node j
+    // reaches its h-th unit when the units ranked before it are busy, taken
+    // as independent with probabilities rho; unit u then receives
+    // r_u = sum_j lambda_j prod_{i<h} rho_{pi_j[i]} while idle and is busy
+    // with probability r_u / (r_u + nu_u).  60 plain fixed-point steps from
+    // rho = min(load, 0.99).
+    std::vector<double> rho(N, std::min(load, 0.99)), r(N, 0.0);
+    for (int it = 0; it < 60; ++it) {
+        std::fill(r.begin(), r.end(), 0.0);
+        for (int j = 0; j < J; ++j) {
+            double pr = 1.0;
+            for (int h = 0; h < N; ++h) {
+                const int u = pref[(size_t)j * N + h];
+                r[u] += lam[j] * pr;
+                pr *= rho[u];
+            }
+        }
+        for (int u = 0; u < N; ++u) rho[u] = r[u] + mu[u] > 0.0 ? r[u] / (r[u] + mu[u]) : 0.0;
+    }
     for (int u = 0; u < N; ++u) {
         float* x = f + (size_t)u * IN;
         for (int i = 0; i < IN; ++i) x[i] = 0.0f;
@@ -176,6 +196,10 @@ void hq_mlp_features_impl(int N, int J, const double* lam, const double* mu, con
         x[13] = (float)(mu[u] / mx);
         x[14] = (float)(N * share[(size_t)u * 9 + 0]);
         x[15] = 1.0f;
+        x[16] = (float)rho[u];
+        x[17] = (float)(Lam > 0.0 ? r[u] / Lam : 0.0);
+        const double lo = std::log(rho[u] / (1.0 - rho[u]));
+        x[18] = (float)(std::min(8.0, std::max(-8.0, lo)) / 8.0);
     }
 }
 

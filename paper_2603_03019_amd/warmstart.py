@@ -82,6 +82,26 @@ def training_set(count: int, *, clustered: float = 0.0, tol: float = 1e-7, chunk
     return np.concatenate(X), np.concatenate(t)
 
 
+def holdout_rmse(net, count: int) -> dict:
+    """RMSE of the predicted utilisations on ``count`` uniform and ``count``
+    clustered deployments outside the training pool (solved to 1e-8)."""
+    out = {}
+    for kind, base, kw in (("uniform", 900000, {}), ("clustered", 950000, CLUSTERED)):
+        insts = [config_instance(5, base + i, **kw) for i in range(count)]
+        ctxs = [hq.create_from_instance(i, inner=hq.HQ_INNER_ONE) for i in insts]
+        hq.hq_solve_batch(ctxs, 1e-8)
+        err = []
+        for inst, ctx in zip(insts, ctxs):
+            rho, _ = hq.hq_marginals(ctx)
+            pred = hq.hq_mlp_forward(net, hq.hq_mlp_features(inst.N, inst.J, inst.lam, inst.nu, inst.pref))
+            err.append(np.asarray(pred, float) - rho)
+            hq.hq_destroy(ctx)
+        e = np.concatenate(err)
+        out[f"val_rmse_{kind}"] = float(np.sqrt(np.mean(e * e)))
+    out["holdout_per_kind"] = count
+    return out
+
+
 def train(X: np.ndarray, t: np.ndarray, *, epochs: int = 40, batch: int = 1024, lr: float = 1e-3,
           seed: int = 0, device: int = -1):
     """A fresh network fitted on (X, t); returns (network, per-epoch loss)."""
@@ -158,6 +178,8 @@ def main(argv=None):
                                                   "else written after solving")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--holdout", type=int, default=400,
+                    help="uniform and clustered deployments outside the pool for the RMSE of the prediction")
     a = ap.parse_args(argv)
     t = time.perf_counter()
     cached = np.load(a.targets, allow_pickle=False) if a.targets and os.path.exists(a.targets) else None
@@ -174,6 +196,9 @@ def main(argv=None):
     s = {"train_solves": a.train, "train_clustered": a.clustered, "train_rows": int(X.shape[0]), "epochs": a.epochs,
          "batch": a.batch, "lr": a.lr,
          "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+    if a.holdout:
+        s["validation"] = holdout_rmse(net, a.holdout)
+        print(f"warmstart: held-out RMSE {s['validation']}", flush=True)
     if a.eval:
         s.update(summarize(evaluate(net, range(50000, 50000 + a.eval), verbose=True)))
     print(json.dumps(s), flush=True)

@@ -67,6 +67,19 @@ def _features_numpy(inst):
     f[:, 13] = nu / nu.max()
     f[:, 14] = N * share[:, 0]
     f[:, 15] = 1.0
+    # independence approximation of the utilisations: unit u receives the
+    # calls whose earlier-ranked units are all busy (busy independently with
+    # probabilities rho), and is busy with probability r_u / (r_u + nu_u)
+    rho = np.full(N, min(load, 0.99))
+    for _ in range(60):
+        before = np.concatenate([np.ones((inst.J, 1)), rho[pref[:, :-1]]], axis=1)
+        reach = np.cumprod(before, axis=1)
+        r = np.zeros(N)
+        np.add.at(r, pref, lam[:, None] * reach)
+        rho = r / (r + nu)
+    f[:, 16] = rho
+    f[:, 17] = r / Lam
+    f[:, 18] = np.clip(np.log(rho / (1.0 - rho)), -8.0, 8.0) / 8.0
     return f
 
 

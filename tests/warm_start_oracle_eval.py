@@ -34,10 +34,12 @@ from paper_2603_03019_amd.instances import config_instance  # noqa: E402
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=100)
+    ap.add_argument("--weights", default="", help="network parameters (default: the shipped ones)")
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_2603_03019_amd", "weights", "warm_mlp_eval.json"))
     a = ap.parse_args()
-    src = os.path.join(ROOT, "paper_2603_03019_amd", "weights", "warm_mlp_eval.json")
-    net = warmstart.load_network()
+    src = a.out if os.path.exists(a.out) else os.path.join(ROOT, "paper_2603_03019_amd", "weights",
+                                                           "warm_mlp_eval.json")
+    net = warmstart.load_network(a.weights) if a.weights else warmstart.load_network()
     rows = []
     for idx in range(50000, 50000 + a.count):
         inst = config_instance(6, idx)
