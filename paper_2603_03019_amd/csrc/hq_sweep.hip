@@ -541,9 +541,7 @@ static uint32_t launch_h(int mode, bool track, const SweepParams& P, const Layer
 // closed form's sweep with the paper's delta tracking).
 uint32_t launch_sweep(int mode, bool track, bool fp32, const SweepParams& P, const LayerArgs& A, void* x,
                       int inner_one, const hqfuse::FuseArgs& F, hipStream_t s) {
-    // (the closed form's look-ahead sweep keeps its long-program layers: the
-    // general kernel reads the look-ahead weights after its neighbours)
-    if (P.b != B || A.stored || (A.general && !P.la) || !P.srec || !P.lrow || A.n < 1 || A.n >= P.N) return 0;
+    if (P.b != B || A.stored || A.general || !P.srec || !P.lrow || A.n < 1 || A.n >= P.N) return 0;
 #define HQ_SW(HV)                                                                     \
     case HV:                                                                          \
         return fp32 ? launch_h<float, HV>(mode, track, P, A, (float*)x, inner_one, F, s) \
