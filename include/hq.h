@@ -61,7 +61,8 @@ enum {
 
 /* reading of Algorithm 1's inner mu(n) loop (delta is never stated) */
 enum {
-    HQ_INNER_CLOSED = 0,  /* the delta -> 0 limit: mu(n) = B / (1 - A) each layer (two passes) */
+    HQ_INNER_CLOSED = 0,  /* the delta -> 0 limit: mu(n) = B / (1 - A) each layer (one pass with
+                             look-ahead sums at the default tile shape up to N = 26, else two) */
     HQ_INNER_ONE = 1,     /* one update per layer (delta = infinity); same fixed point */
     HQ_INNER_LITERAL = 2  /* the inner loop of Algorithm 1 as written, tolerance opts.delta
                              (two passes; the loop itself runs on the layer's sums) */

@@ -91,8 +91,8 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Reduce six per-thread values over the work-group (sum, sum, max, max,
 // sum, sum) and store them as this work-group's partial.  No fence: the
-// finalize kernel that reads the partials runs after this kernel on the
-// same stream.
+// finalize kernel (or, after a small layer, the next layer's launch) that
+// reads the partials runs after this kernel on the same stream.
 __device__ void block_partial(double a0, double a1, double a2, double a3, double* partials, double a4 = 0.0,
                               double a5 = 0.0) {
     __shared__ double s_red[HQ_NPART][HQ_WG / 64];
