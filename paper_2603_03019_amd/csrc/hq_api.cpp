@@ -132,7 +132,7 @@ struct hq_ctx {
     // device memory
     double* x64 = nullptr;
     float* x32 = nullptr;
-    double *d_nu = nullptr, *d_mu_lo = nullptr, *d_tcoef = nullptr, *d_scal = nullptr, *d_part = nullptr;
+    double *d_nu = nullptr, *d_tcoef = nullptr, *d_scal = nullptr, *d_part = nullptr;
     double *d_scale64 = nullptr, *d_scale32 = nullptr, *d_rho = nullptr, *d_xu = nullptr, *d_given = nullptr;
     uint32_t *d_binom = nullptr, *d_layer_off = nullptr, *d_lo_qstart = nullptr, *d_prog_off = nullptr,
              *d_orig_bit = nullptr, *d_seg_desc = nullptr, *d_segoff = nullptr, *d_seg_prog = nullptr;
@@ -162,7 +162,7 @@ struct hq_ctx {
 
     ~hq_ctx() { release(); }
     void release() {
-        void* ptrs[] = {x64,       x32,        d_nu,       d_mu_lo,    d_tcoef,     d_scal,     d_part,
+        void* ptrs[] = {x64,       x32,        d_nu,       d_tcoef,     d_scal,     d_part,
                         d_scale64, d_scale32,  d_rho,      d_xu,       d_given,     d_binom,    d_layer_off,
                         d_lo_qstart, d_prog_off, d_prog, d_orig_bit, d_lo_unrank, d_lo_rank, d_nodes,
                         d_counters, d_seg_desc, d_segoff,   d_coefs,     d_seg_prog, d_G,
@@ -274,7 +274,6 @@ void setup_params(hq_ctx* c) {
     P.lo_unrank = c->d_lo_unrank;
     P.lo_rank = c->d_lo_rank;
     P.lo_qstart = c->d_lo_qstart;
-    P.mu_lo = c->d_mu_lo;
     P.tcoef = c->d_tcoef;
     P.seg_desc = c->d_seg_desc;
     P.seg_prog = reinterpret_cast<const uint2*>(c->d_seg_prog);
@@ -403,14 +402,9 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     for (int n = 0; n < 32; ++n)
         for (int k = 0; k <= n; ++k) tb[n * 32 + k] = (uint32_t)binom_d(n, k);
     const std::vector<uint32_t>& layer_off = lay.layer_off;
-    const uint32_t lo = 1u << b;
     const std::vector<uint16_t>& lo_unrank = lay.lo_unrank;
     const std::vector<uint16_t>& lo_rank = lay.lo_rank;
     const std::vector<uint32_t>& lo_qstart = lay.lo_qstart;
-    std::vector<double> mu_lo(lo, 0.0);
-    for (uint32_t L = 0; L < lo; ++L)
-        for (int u = 0; u < b; ++u)
-            if ((L >> u) & 1u) mu_lo[L] += c->nu[u];
     const std::vector<uint32_t>& segoff = lay.segoff;
     const std::vector<uint32_t>& seg_desc = lay.seg_desc;
     // per segment: where its tile's program starts and how many terms it has
@@ -534,7 +528,6 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         if (o.precision != HQ_FP32) c->x64 = dalloc<double>(S);
         if (o.precision != HQ_FP64) c->x32 = dalloc<float>(S);
         c->d_nu = dalloc<double>(N);
-        c->d_mu_lo = dalloc<double>(lo);
         c->d_tcoef = dalloc<double>(tcoef.size());
         c->d_scal = dalloc<double>(10 * (N + 1) + 8);
         // two halves of max_groups partials each (consecutive layer launches of an
@@ -570,7 +563,6 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         }
         hipStream_t s = c->stream;
         h2d(c->d_nu, c->nu, s);
-        h2d(c->d_mu_lo, mu_lo, s);
         h2d(c->d_tcoef, tcoef, s);
         h2d(c->d_scale64, s64, s);
         h2d(c->d_scale32, s32, s);

@@ -61,7 +61,6 @@ struct SweepParams {
     const uint16_t* lo_unrank;   // [2^b] low patterns ordered by (popcount, value)
     const uint16_t* lo_rank;     // [2^b] rank of a low pattern inside its popcount class
     const uint32_t* lo_qstart;   // [b+2] start of popcount class q in lo_unrank
-    const double* mu_lo;         // [2^b] service-rate sum of a low pattern
     const double* tcoef;         // [2^H * N] per-tile dispatch coefficients
     const uint32_t* seg_desc;    // per layer and work-group: (T << 4) | q
     const uint32_t* segoff;      // [(b+1) * 2^H] absolute start of segment (T, q)
