@@ -100,3 +100,31 @@ def test_batch_product_start_matches_oracle():
     for inst, ref, ctx, info, ci in zip(insts, refs, ctxs, infos, cold_infos):
         assert np.abs(hq.hq_state(ctx) - ref.P).sum() <= 1e-9, inst.N
         assert info["iterations"] <= ci["iterations"]
+
+
+def test_full_benchmark_batch_answers_pass_the_oracle():
+    """The bench's batched workload in full: 256 deployments with N ~
+    U{12..18}, J = 100, in one batched solve to 1e-12.  Every answer's
+    balance residual of (1), recomputed by the oracle with its own
+    Algorithm-3 coefficients, is <= 2e-12; one deployment of each size is
+    also compared state by state with the oracle's solve (L1 <= 1e-10)."""
+    insts = [config_instance(4, i) for i in range(256)]
+    say(f"case full batch: 256 deployments, N {min(i.N for i in insts)}..{max(i.N for i in insts)}")
+    ctxs = [hq.create_from_instance(i, inner=hq.HQ_INNER_ONE) for i in insts]
+    st, infos = hq.hq_solve_batch(ctxs, 1e-12)
+    assert st == hq.HQ_OK
+    worst, seen = 0.0, set()
+    for k, (inst, ctx, info) in enumerate(zip(insts, ctxs, infos)):
+        assert info["residual"] <= 1e-12, (k, info["residual"])
+        P = hq.hq_state(ctx)
+        r = cpu.residual(inst, P)
+        worst = max(worst, r)
+        assert r <= 2e-12, (k, inst.N, r)
+        if inst.N not in seen:
+            seen.add(inst.N)
+            ref = cpu.solve(inst, tol=1e-12, inner="one")
+            l1 = np.abs(P - ref.P).sum()
+            say(f"  N={inst.N} (deployment {k}): L1 vs oracle {l1:.2e}")
+            assert l1 <= 1e-10, (k, inst.N, l1)
+        hq.hq_destroy(ctx)
+    say(f"  largest oracle residual over the 256 answers: {worst:.3e}")
