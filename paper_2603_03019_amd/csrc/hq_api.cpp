@@ -428,8 +428,9 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
     c->fuse = !(nofuse && nofuse[0] == '1');
     // the default-shape sweep kernels serve H = 6..16 (N = 16..26); from
     // H = 17 the general layer kernel measured faster (N = 27: 7.07 against
-    // 7.59 ms per outer iteration, N = 30: 52.0 against 56.6 ms)
-    if (b == HQ_SWEEP_B && c->H >= 6 && c->H <= 16 && !(legacy && legacy[0] == '1')) {
+    // 7.59 ms per outer iteration, N = 30: 52.0 against 56.6 ms).  They
+    // address the programs with 32-bit byte offsets.
+    if (b == HQ_SWEEP_B && c->H >= 6 && c->H <= 16 && prog.size() < (1ull << 27) && !(legacy && legacy[0] == '1')) {
         lrow = hqsweeptab::low_rows(lay, c->nu, 8);
         lrow32 = hqsweeptab::low_rows(lay, c->nu, 4);
         srec = hqsweeptab::seg_records(lay, prog_off, c->nu);
@@ -469,6 +470,9 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
             }
         }
     }
+    // the look-ahead closed form (one pass per layer) needs the default-shape
+    // sweep, which accumulates its sums while it writes
+    const bool lookahead = o.inner == HQ_INNER_CLOSED && !srec.empty() && !(nola && nola[0] == '1');
     int top = o.stored_layers;
     if (top == 0) {
         uint64_t budget = HQ_STORE_BYTES;
@@ -495,11 +499,13 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
             c->layers[n].stored = 1;
             c->layers[n].coef_base = coef_total;
             coef_total += (unsigned long long)N * c->layers[n].count;
-        } else if (num[n] >= HQ_GENERAL_TERMS * den[n]) {
+        } else if (num[n] >= HQ_GENERAL_TERMS * den[n] && !lookahead) {
             // long programs: the general kernel, which forms each busy unit's
             // coefficient next to its neighbour value, measured faster there
             // (N = 26 clustered, layers 16..19: 252, 213, 163, 133 against
-            // 259, 228, 174, 144 us)
+            // 259, 228, 174, 144 us).  The look-ahead closed form keeps the
+            // sweep, whose look-ahead pairs arrive as one 16-byte load per
+            // state (N = 26: 1.146 against 1.152 s to 1e-8).
             c->layers[n].general = 1;
         }
     }
@@ -554,8 +560,7 @@ hq_status create_impl(int N, int J, const double* lam, const double* mu, const i
         c->d_counters = dalloc<unsigned int>(N + 1);
         // the look-ahead closed form (one pass per layer) needs the default-shape
         // sweep, which accumulates its sums while it writes
-        if (o.inner == HQ_INNER_CLOSED && !srec.empty() && !(nola && nola[0] == '1'))
-            c->d_la = dalloc<double>(2 * S);
+        if (lookahead) c->d_la = dalloc<double>(2 * S);
         if (!srec.empty()) {
             c->d_srec = dalloc<uint32_t>(srec.size());
             c->d_lrow = dalloc<LowRow>(lrow.size());

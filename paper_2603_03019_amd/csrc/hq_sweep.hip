@@ -67,6 +67,15 @@ __device__ __forceinline__ double rld(double v, int i) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// The lane index, as a value the compiler cannot hoist out of a loop (the
+// empty volatile asm): offsets derived from it are formed where a load
+// needs them instead of being held in registers across the state loop.
+__device__ __forceinline__ uint32_t lane_now() {
+    uint32_t l = threadIdx.x & 63u;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     return v;
@@ -146,10 +155,11 @@ __device__ __forceinline__ Scal load_scal(const SweepParams& P, int n, int inner
 
 // Sum of the rates of unit u's program terms whose low mask lies in L (nL
 // = ~L).  The tile's first 64 terms are held lane-parallel (mask in tmk,
-// rate in trt); terms past 64 are read as scalar loads.
-__device__ __forceinline__ double unit_terms(const HQ_CONST ProgTerm* pg, uint32_t pov, uint32_t tmk, double trt,
-                                             int u, uint32_t nL) {
-    const uint32_t i0 = rl(pov, u), i1 = rl(pov, u + 1);
+// rate in trt); terms past 64 are read as scalar loads.  pov: lane u holds
+// the absolute index of unit u's first term, pstart that of the tile's.
+__device__ __forceinline__ double unit_terms(const HQ_CONST ProgTerm* pg, uint32_t pov, uint32_t pstart, uint32_t tmk,
+                                             double trt, int u, uint32_t nL) {
+    const uint32_t i0 = rl(pov, u) - pstart, i1 = rl(pov, u + 1) - pstart;
     const uint32_t ir = i1 < 64u ? i1 : 64u;
     double c = 0.0;
     for (uint32_t i = i0; i < ir; ++i) {
@@ -186,7 +196,8 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
                                         const double tcv, const uint32_t pov, const uint32_t tmk, const double trt,
                                         const Scal& s, double* wlds, T* stage, const uint16_t* s_rank,
                                         double& acc0, double& acc1, double& acc2, double& acc3, double& acc4,
-                                        double& acc5, __amdgpu_buffer_rsrc_t lar, const uint32_t lbase) {
+                                        double& acc5, __amdgpu_buffer_rsrc_t lar, const uint32_t lbase,
+                                        const double* s_nu) {
     constexpr uint32_t SZ = sizeof(T);
     const int lane = threadIdx.x & 63;
     const uint32_t desc = rl(rec, HQ_REC_DESC);
@@ -216,19 +227,22 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
     const int k1 = hm1 ? __builtin_ctz(hm1) : -1;
     const uint32_t o_t0 = k0 >= 0 ? (rl(rec, HQ_REC_HI + k0) - base) * SZ : o_self;
     const uint32_t o_t1 = k1 >= 0 ? (rl(rec, HQ_REC_HI + k1) - base) * SZ : o_self;
-    const HQ_CONST ProgTerm* pg = cro(P.prog) + rl(rec, HQ_REC_PSTART);
+    const uint32_t pstart = rl(rec, HQ_REC_PSTART);
+    const HQ_CONST ProgTerm* pg = cro(P.prog) + pstart;
     // weights: lane u < N holds unit u's; alpha-side for busy units (tile
     // coefficient), beta-side for idle ones (service rate)
-    const double nu_l = lane < P.N ? cro(P.nu)[lane] : 0.0;
+    const double nu_l = s_nu[lane];
     const bool busy_hi = lane >= B && lane < P.N && ((Tb >> (lane - B)) & 1u);
     // (PASS1 keeps the two sides apart, side factors applied at the end)
     const double wA = MODE == S_PASS1 ? (busy_hi ? tcv : nu_l) : (busy_hi ? s.wa * tcv : s.wb * nu_l);
     // The previous segment's LDS reads of this wave are done (a wave's LDS
     // operations complete in order).  Then the weights go to this wave's
     // slots: low unit l busy at [l], idle at [16 + l]; high unit B + k at
-    // [32 + k]; and the
-    // low-neighbour segments (T, q - 1) of layer n - 1 and (T, q + 1) of
-    // layer n + 1 go to this wave's staging area, one after the other.
+    // [32 + k]; and the low-neighbour segments (T, q - 1) of layer n - 1 and
+    // (T, q + 1) of layer n + 1 go to this wave's staging area, one after the
+    // other.  (Issuing all of a segment's staging loads before the first LDS
+    // write needs up to 16 more registers here, which spill in the look-ahead
+    // instantiation and made it slower.)
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (lane < B) {
@@ -311,7 +325,7 @@ __device__ __forceinline__ void segment(const SweepParams& P, __amdgpu_buffer_rs
         while (um) {
             const int u = __builtin_ctz(um);
             um &= um - 1u;
-            double c = unit_terms(pg, pov, tmk, trt, u, nL);
+            double c = unit_terms(pg, pov, pstart, tmk, trt, u, nL);
             double v;
             if (u < B) {
                 const bool bz = (L >> u) & 1u;
@@ -370,8 +384,10 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(MODE == S
     __shared__ T s_stage[WAVES][HQ_SWEEP_STAGE];  // per wave: segments (T, q - 1) and (T, q + 1)
     __shared__ uint16_t s_rank[1 << B];
     __shared__ double s_red[HQ_NPART][WAVES];
+    __shared__ double s_nu[64];  // service rates, 0 past N
     const int tid = threadIdx.x, lane = tid & 63;
     for (int i = tid; i < (1 << B); i += HQ_WG) s_rank[i] = P.lo_rank[i];
+    if (tid < 64) s_nu[tid] = tid < P.N ? P.nu[tid] : 0.0;
     __syncthreads();
     const int n = A.n;
     // the previous layer's scalars, when its finalize launch is fused into this one
@@ -406,41 +422,58 @@ __global__ __launch_bounds__(HQ_WG) __attribute__((amdgpu_waves_per_eu(MODE == S
         step = (G >> 3) * WAVES;
     }
     double* wlds = s_w + wv * 64;
-    // the record of segment i + 2 and the tile coefficients and program
-    // offsets of segment i + 1 are in flight while segment i is processed
-    const uint32_t* recs = P.srec + (size_t)A.desc_base * HQ_REC_WORDS;
+    // The record of segment i + 2 and the tile coefficients and program
+    // offsets of segment i + 1 are in flight while segment i is processed.
+    // They are read through buffer resources at clamped offsets (always
+    // inside the arrays): no lane-masked branch around a load, and no
+    // per-lane 64-bit address held across the state loop (such addresses
+    // were spilled to scratch and reloaded, with a full wait, per segment).
+    // A segment index past the wave's share reads the share's last record,
+    // which nothing then uses.
+    const __amdgpu_buffer_rsrc_t recr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(P.srec + (size_t)A.desc_base * HQ_REC_WORDS), 0, -1, RSRC_W3);
+    const __amdgpu_buffer_rsrc_t tcr = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(P.tcoef), 0, -1, RSRC_W3);
+    const __amdgpu_buffer_rsrc_t por =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(P.prog_off), 0, -1, RSRC_W3);
+    const __amdgpu_buffer_rsrc_t pgr = __builtin_amdgcn_make_buffer_rsrc(const_cast<ProgTerm*>(P.prog), 0, -1, RSRC_W3);
+    const uint32_t last = end > 0u ? end - 1u : 0u;
+    const uint32_t Nu = (uint32_t)P.N;
     auto load_rec = [&](uint32_t si) -> uint32_t {
-        return (si < end && lane < HQ_REC_WORDS) ? recs[(size_t)si * HQ_REC_WORDS + lane] : 0u;
+        const uint32_t l = lane_now();
+        return __builtin_amdgcn_raw_buffer_load_b32(recr, min(l, (uint32_t)HQ_REC_WORDS - 1u) * 4u,
+                                                    min(si, last) * (uint32_t)(HQ_REC_WORDS * 4), 0);
     };
     // tile data of a segment, lane-parallel: lane u its tile coefficient and
-    // first program term, lane i the mask and rate of program term i < 64
+    // the absolute index of its first program term, lane i the mask and rate
+    // of program term i < 64 (lanes past the counts hold copies of the last
+    // entry, which nothing reads)
     struct Tile {
         double tcv, trt;
         uint32_t pov, tmk;
     };
-    auto load_tile = [&](uint32_t si, uint32_t rec) -> Tile {
+    auto load_tile = [&](uint32_t rec) -> Tile {
         Tile tl{0.0, 0.0, 0u, 0u};
-        if (si >= end) return tl;
+        const uint32_t l = lane_now();
         const uint32_t Tb = rl(rec, HQ_REC_DESC) >> 4;
-        if (lane < P.N) tl.tcv = P.tcoef[(size_t)Tb * P.N + lane];
+        tl.tcv = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(tcr, min(l, Nu - 1u) * 8u,
+                                                                                 Tb * Nu * 8u, 0));
         if (rl(rec, HQ_REC_PMASK) != 0u) {
             const uint32_t pstart = rl(rec, HQ_REC_PSTART), pcount = rl(rec, HQ_REC_PCOUNT);
-            if (lane <= P.N) tl.pov = P.prog_off[(size_t)Tb * (P.N + 1) + lane] - pstart;
-            if ((uint32_t)lane < pcount) {
-                tl.tmk = P.prog[pstart + lane].mask;
-                tl.trt = P.prog[pstart + lane].rate;
-            }
+            tl.pov = __builtin_amdgcn_raw_buffer_load_b32(por, min(l, Nu) * 4u, Tb * (Nu + 1u) * 4u, 0);
+            const u32x4 tm = __builtin_amdgcn_raw_buffer_load_b128(pgr, min(l, pcount - 1u) * 16u, pstart * 16u, 0);
+            tl.tmk = tm[0];
+            tl.trt = __builtin_bit_cast(double, (unsigned long long)tm[2] | ((unsigned long long)tm[3] << 32));
         }
         return tl;
     };
     T* stage = s_stage[wv];
     uint32_t rec0 = load_rec(begin), rec1 = load_rec(begin + step);
-    Tile t0 = load_tile(begin, rec0);
+    Tile t0 = load_tile(rec0);
     for (uint32_t si = begin; si < end; si += step) {
         const uint32_t rec2 = load_rec(si + 2 * step);
-        const Tile t1 = load_tile(si + step, rec1);
+        const Tile t1 = load_tile(rec1);
         segment<T, MODE, TRACK, HF>(P, xr, rowr, base, rec0, t0.tcv, t0.pov, t0.tmk, t0.trt, s, wlds, stage, s_rank,
-                                    acc0, acc1, acc2, acc3, acc4, acc5, lar, lbase);
+                                    acc0, acc1, acc2, acc3, acc4, acc5, lar, lbase, s_nu);
         rec0 = rec1;
         rec1 = rec2;
         t0 = t1;
