@@ -176,11 +176,12 @@ def batched_leg(hq, config_instance, tol: float, count: int = 256):
 
     insts = [config_instance(4, i) for i in range(count)]
     ctxs = [hq.create_from_instance(i, inner=hq.HQ_INNER_ONE) for i in insts]
-    hq.hq_solve_batch(ctxs, tol)  # first call: tile autotune and graph capture
+    hq.hq_solve_batch(ctxs, tol)  # first call: work-group size autotune and graph capture
     torch.cuda.synchronize()
     t = time.perf_counter()
     _, infos = hq.hq_solve_batch(ctxs, tol)
     batch_s = time.perf_counter() - t
+    block = hq.hq_batch_last_block()
     t = time.perf_counter()
     seq = [hq.hq_solve(c, tol) for c in ctxs]
     seq_s = time.perf_counter() - t
@@ -190,6 +191,8 @@ def batched_leg(hq, config_instance, tol: float, count: int = 256):
     return {
         "workload": f"{count} deployments, N~U{{12..18}} (total {sum(1 << i.N for i in insts)} states), "
                     f"J=100 uniform, mu_i~U[0.8,1.2], load 0.6, tol {tol:g}",
+        "tile_low_bits": 10,
+        "work_group_threads": block,
         "batched_s": batch_s,
         "sequential_s": seq_s,
         "speedup_vs_sequential": seq_s / batch_s,

@@ -262,6 +262,16 @@ hq_status hq_solve_batch(hq_ctx* const* ctxs, int count, double tol, hq_info* in
 #define HQ_NOALLOC_MAX_BATCH 256
 hq_status hq_solve_batch_noalloc(hq_ctx* const* ctxs, int count, double tol, hq_info* infos);
 
+/*
+ * Shape of the most recent batched solve in this process, for reports:
+ * the work-group size (threads) it ran with, 0 before any batched solve.
+ * The batch kernel sweeps with 10 low bits per tile; the work-group size
+ * is timed over 256, 512 and 1024 threads on the first hq_solve_batch of
+ * each batch signature (precision, count, sorted unit counts) and reused
+ * for that signature afterwards.
+ */
+int hq_batch_last_block(void);
+
 /* Release a context (NULL-safe). */
 void hq_destroy(hq_ctx* ctx);
 

@@ -2,6 +2,7 @@
 // the orchestration of Algorithm 1 on one GPU.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -896,6 +897,7 @@ struct BatchRes {
 std::mutex g_batch_mu;
 std::map<int, BatchRes> g_batch;
 std::map<std::string, int> g_batch_tuned;  // batch signature -> work-group size
+std::atomic<int> g_batch_last_block{0};    // work-group size of the last batched solve
 
 BatchRes& batch_res(int device, int count) {
     BatchRes& r = g_batch[device];
@@ -1075,6 +1077,7 @@ hq_status batch_group(const std::vector<hq_ctx*>& cs, const std::vector<int>& po
         (void)hipEventDestroy(e1);
         g_batch_tuned[sig] = block;
     }
+    g_batch_last_block.store(block);
     auto t0 = std::chrono::steady_clock::now();
     HQ_HIP(hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, stream));
     std::vector<BatchOut> outs(count);
@@ -1506,6 +1509,8 @@ hq_status hq_solve_batch(hq_ctx* const* ctxs, int count, double tol, hq_info* in
         return fail(HQ_ERR_DEVICE, std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
     }
 }
+
+int hq_batch_last_block(void) { return g_batch_last_block.load(); }
 
 hq_status hq_solve_batch_noalloc(hq_ctx* const* ctxs, int count, double tol, hq_info* infos) {
     if (count > HQ_NOALLOC_MAX_BATCH)

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "HQ_OK", 1: "HQ_ERR_INVALID_ARG", 2: "HQ_ERR_OUT_OF_MEMORY", 
 
 # every symbol include/hq.h declares
 EXPORTED = ["hq_default_options", "hq_create", "hq_solve", "hq_marginals", "hq_queue", "hq_dispatch", "hq_state",
-            "hq_solve_batch", "hq_solve_batch_noalloc",
+            "hq_solve_batch", "hq_solve_batch_noalloc", "hq_batch_last_block",
             "hq_destroy", "hq_last_error", "hq_iterate", "hq_reset", "hq_residual", "hq_conditional",
             "hq_layer_scalars", "hq_state_device", "hq_num_units", "hq_mlp_features", "hq_mlp_create",
             "hq_mlp_destroy", "hq_mlp_get_params", "hq_mlp_set_params", "hq_mlp_forward", "hq_mlp_gradient",
@@ -97,6 +97,8 @@ def load(path: str = LIB_PATH):
     L.hq_solve_batch.restype = c_int
     L.hq_solve_batch_noalloc.argtypes = [ctypes.POINTER(vp), c_int, c_double, ctypes.POINTER(hq_info)]
     L.hq_solve_batch_noalloc.restype = c_int
+    L.hq_batch_last_block.argtypes = []
+    L.hq_batch_last_block.restype = c_int
     L.hq_destroy.argtypes = [vp]
     L.hq_destroy.restype = None
     L.hq_last_error.argtypes = []
@@ -280,6 +282,11 @@ def hq_solve_batch_noalloc(ctxs: Sequence[Context], tol: float, *, allow_not_con
     st = load().hq_solve_batch_noalloc(arr, n, float(tol), infos)
     _check(st, (HQ_OK, HQ_ERR_NOT_CONVERGED) if allow_not_converged else (HQ_OK,))
     return st, [infos[i].as_dict() for i in range(n)]
+
+
+def hq_batch_last_block() -> int:
+    """Work-group size of the most recent batched solve (0 before any)."""
+    return int(load().hq_batch_last_block())
 
 
 def hq_destroy(ctx: Context):

@@ -113,6 +113,7 @@ def test_full_benchmark_batch_answers_pass_the_oracle():
     ctxs = [hq.create_from_instance(i, inner=hq.HQ_INNER_ONE) for i in insts]
     st, infos = hq.hq_solve_batch(ctxs, 1e-12)
     assert st == hq.HQ_OK
+    assert hq.hq_batch_last_block() in (256, 512, 1024)
     worst, seen = 0.0, set()
     for k, (inst, ctx, info) in enumerate(zip(insts, ctxs, infos)):
         assert info["residual"] <= 1e-12, (k, info["residual"])
