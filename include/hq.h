@@ -228,10 +228,10 @@ hq_status hq_state(const hq_ctx* ctx, double* P);
  * Solve several instances (an uneven batch of candidate deployments) to tol
  * in one persistent launch: Algorithm 1 (initial iterate, Gauss-Seidel
  * layer sweeps with the update (12)-(14), balance-residual stop on (1)) for
- * every instance, the instances independent of each other.  Every context must be on the same device and must have been
- * created with HQ_FP64 or HQ_FP32 storage, the residual stopping rule and the
- * closed or one-update inner form (HQ_ERR_INVALID_ARG otherwise).  infos
- * (nullable) [count].
+ * every instance, the instances independent of each other.  Every context
+ * must be on the same device and must have been created with HQ_FP64 or
+ * HQ_FP32 storage, the residual stopping rule and the closed or one-update
+ * inner form (HQ_ERR_INVALID_ARG otherwise).  infos (nullable) [count].
  * A large instance is shared by up to 16 work-groups that meet at a barrier
  * after every layer; the results agree with hq_solve to rounding, and a
  * repeated batch gives bitwise the same results.  A barrier wait that runs
