@@ -28,6 +28,11 @@ def test_library_exports_every_declared_symbol():
     assert sorted(hq.EXPORTED) == names
 
 
+def test_batch_shape_report_before_any_batch():
+    # no batched solve has run in this process (no device here)
+    assert hq.hq_batch_last_block() == 0
+
+
 def test_default_options():
     o = hq.hq_default_options()
     assert o.precision == hq.HQ_FP64 and o.inner == hq.HQ_INNER_ONE and o.init == hq.HQ_INIT_UNIFORM
