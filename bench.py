@@ -405,8 +405,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(inst.N, args.precision),
-            "kernel": "layer sweep: sweep_kernel (computed-coefficient layers) and layer_kernel (stored "
-                      f"layers){' with the look-ahead sums of the closed form' if args.inner == 'closed' else ''}, per outer "
+            "kernel": "layer sweep: sweep_kernel (short-program layers) and layer_kernel (long-program and "
+                      f"stored layers){' with the look-ahead sums of the closed form' if args.inner == 'closed' else ''}, "
+                      "per outer "
                       f"iteration of {inst.N - 1} layer launches and their finalize launches",
             "bytes_per_iteration": bytes_it,
             "us_per_iteration": per_it * 1e6,
